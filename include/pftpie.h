@@ -1,0 +1,199 @@
+/*
+ * pftpie.h -- C ABI of the MI355X (gfx950) batched 2-D partial Fourier
+ * transform and the PIE sweep built on it.
+ *
+ * Method: Parada, Wu Fung, Osher, "Fast Partial Fourier Transforms for
+ * Large-Scale Ptychography" (arXiv 2408.03532).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Complex data are interleaved complex64: {float re, float im}, the memory
+ *    of torch.complex64.  Arrays are dense, row-major (C order).
+ *  - Window: a transform of an n x n patch keeps m coefficients per axis,
+ *    the frequencies t_c = c - floor(m/2), c = 0..m-1, stored in that
+ *    centred order, row-major [c1][c2] (axis 0 = rows).  This is the centred
+ *    m x m crop of an fftshift-ed 2-D DFT (the paper's Fig. 2 and the data
+ *    cropping of Algorithm 3).  Spatial indices run 0..n-1 from the patch's
+ *    top-left corner.
+ *  - Pointers named *_dev / data pointers are device pointers; host_* are
+ *    host pointers.  The caller owns every data buffer and workspace; the
+ *    library owns plans and scans (device twiddle tables, positions).
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL = the default stream) and never synchronises with the host except
+ *    plan / scan creation and destruction.  No call other than plan / scan
+ *    creation allocates device memory.
+ *  - Errors: arguments are validated on the host before anything is
+ *    enqueued; a non-OK status means nothing was enqueued and no output was
+ *    touched.  pftpie_last_error() gives a thread-local message for the last
+ *    failure.  A device fault surfaces as PFTPIE_E_DEVICE from a later call
+ *    or at the caller's synchronisation.  Nothing throws across the ABI.
+ *  - Plans and scans are immutable after creation and may be shared between
+ *    streams; workspaces may not.  Plans and scans belong to the device that
+ *    was current when they were created.
+ */
+#ifndef PFTPIE_H
+#define PFTPIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PFTPIE_OK = 0,
+  PFTPIE_E_INVALID = 1,      /* bad argument: shape, pointer, range, alias */
+  PFTPIE_E_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  PFTPIE_E_NOMEM = 3,        /* device or host allocation failed (creation) */
+  PFTPIE_E_DEVICE = 4        /* HIP runtime error */
+} pftpie_status;
+
+/* Arithmetic of the contractions.  FP32: float operands and accumulation.
+ * SPLIT_BF16 / SPLIT_FP16: each operand x is split into hi = RNE(x) and
+ * lo = RNE(x - hi) in the 16-bit type; products are hi*hi + hi*lo + lo*hi,
+ * accumulated in float.  Twiddles are generated in double in every mode. */
+typedef enum {
+  PFTPIE_FP32 = 0,
+  PFTPIE_SPLIT_BF16 = 1,
+  PFTPIE_SPLIT_FP16 = 2
+} pftpie_precision;
+
+typedef struct pftpie_plan_s* pftpie_plan;
+typedef struct pie_scan_s* pie_scan;
+
+const char* pftpie_status_string(pftpie_status s);
+const char* pftpie_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Partial transform of n x n patches to their m x m low-frequency window.
+ * The exact DFT restricted to the window (Appendix A, 2-D DFT; Sec. 3.1.1,
+ * 1-D DFT): the quantity the paper's PFT approximates (Sec. 3.1, Fig. 2).
+ *
+ * pftpie_plan_create: 1 <= m <= n <= 4096.  Builds the partial DFT matrix
+ *   F_m[c][k] = exp(-2 pi i ((t_c k) mod n) / n) in double (integer
+ *   reduction of the phase first), rounds it to the plan's precision and
+ *   uploads it in the kernels' tile order.  Allocates device memory on the
+ *   current device; synchronous.  *out is NULL on failure. */
+pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec,
+                                 pftpie_plan* out);
+pftpie_status pftpie_plan_destroy(pftpie_plan plan);
+/* Query a plan's sizes and precision (any output pointer may be NULL). */
+pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,
+                               pftpie_precision* prec);
+
+/* Forward: y_b = F_m psi_b F_m^T for b < batch.
+ *   psi: device complex64 [batch][n][n]; y: device complex64 [batch][m][m].
+ *   batch >= 0 (0 enqueues nothing).  psi and y must not overlap and must be
+ *   8-byte aligned (16-byte alignment enables the vector-load path). */
+pftpie_status pft2d_forward(pftpie_plan plan, const void* psi, void* y,
+                            int64_t batch, void* stream);
+
+/* Adjoint: psi_b = F_m^H y_b conj(F_m) (no 1/n^2 factor), the exact adjoint
+ * of pft2d_forward, so <F x, y> = <x, F^H y>, and F_m F_m^H = n^2 I.
+ *   y: device complex64 [batch][m][m]; psi: device complex64 [batch][n][n]. */
+pftpie_status pft2d_adjoint(pftpie_plan plan, const void* y, void* psi,
+                            int64_t batch, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Uneven batch: many patches of different sizes in one launch.
+ * Descriptor i: patch side n, window m, and element offsets (complex
+ * elements) of its input and output inside the packed `in` / `out` arrays.
+ * Forward: in holds n*n, out holds m*m elements per descriptor; adjoint the
+ * reverse.  Every (n, m) pair present must be one of the plans given.
+ *
+ * pftpie_group_create: validates the descriptors on the host (sizes in
+ *   range, blocks inside the packed arrays, outputs disjoint), orders the
+ *   work longest-first and uploads it.  in_len / out_len are the lengths of
+ *   the packed arrays in complex elements.  Synchronous, allocates. */
+typedef struct {
+  int32_t n, m;
+  int64_t in_offset, out_offset;
+} pft2d_desc;
+typedef struct pft2d_group_s* pft2d_group;
+
+pftpie_status pftpie_group_create(const pftpie_plan* plans, int32_t nplans,
+                                  const pft2d_desc* host_desc, int64_t count,
+                                  int64_t in_len, int64_t out_len, int32_t adjoint,
+                                  pft2d_group* out);
+pftpie_status pftpie_group_destroy(pft2d_group group);
+/* Run the whole uneven batch in one persistent launch (all plans must share
+ * one precision).  in / out: device complex64 packed arrays. */
+pftpie_status pft2d_group_run(pft2d_group group, const void* in, void* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* PIE / ePIE sweep (Sec. 2.1: projection eq. (3), objective eq. (4), object
+ * and probe iterates eqs. (5)-(6); data cropping of Algorithm 3).
+ *
+ * pie_scan_create: positions host_pos int32 [J][2] = top-left (row, col) of
+ *   each n x n window inside an H x W object; 0 <= row <= H-n and
+ *   0 <= col <= W-n are required (no wrap-around).  Uploads the positions.
+ *   The plan (its n, m, precision) is referenced, not copied: keep it alive. */
+pftpie_status pie_scan_create(pftpie_plan plan, const int32_t* host_pos, int32_t J,
+                              int32_t H, int32_t W, pie_scan* out);
+pftpie_status pie_scan_destroy(pie_scan scan);
+
+typedef struct {
+  int32_t batch;  /* positions per accumulate-and-apply chunk: 1 = the
+                     sequential iterate of eq. (5); J = fully batched */
+  int32_t norm;   /* 0: O += beta * sum conj(P) dpsi (eq. (5));
+                     1: divided by sum |P|^2 + alpha * max (overlap-normalised) */
+  float beta;     /* object step */
+  float gamma;    /* probe step; 0 = probe fixed (non-blind PIE) */
+  float alpha;    /* denominator regulariser relative to the max (norm == 1) */
+} pie_params;
+
+/* Bytes of device workspace pie_sweep needs for these parameters. */
+pftpie_status pie_workspace_size(pie_scan scan, const pie_params* p, size_t* bytes);
+
+/* One sweep over all J positions, in chunks of p->batch of the order
+ * order_dev (device int32 permutation of [0, J), or NULL for scan order).
+ * For each position j of a chunk, against the object and probe as they
+ * were at the chunk start:
+ *   psi = P * O[window j];  u = F_m psi F_m^T;
+ *   u' = amp_j * u / |u|  (amp_j where u == 0);
+ *   dpsi = F_m^H (u' - u) conj(F_m) / n^2     (pseudo-inverse correction);
+ * then O += beta * sum_j conj(P) dpsi (norm 0) or that sum divided by
+ * sum_j |P|^2 + alpha max (norm 1); with gamma > 0 likewise
+ * P += gamma * sum_j conj(O_j) dpsi (divided by sum |O_j|^2 + alpha max).
+ *   object: device complex64 [H][W], updated in place.
+ *   probe:  device complex64 [n][n], updated in place when gamma > 0.
+ *   amp:    device float32 [J][m][m], the square roots of the centred m x m
+ *           crop of the measured intensities (indexed by position j).
+ *   stats_dev: device double[4] or NULL, written with
+ *           {Phi, ||O_after - O_before||^2, ||O_before||^2, n_nonfinite},
+ *           Phi = sum_j sum (|u_j| - amp_j)^2 / (J n^2) (eq. (4)).
+ *   workspace: device memory of at least pie_workspace_size bytes,
+ *           256-byte aligned. */
+pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* amp,
+                        const int32_t* order_dev, const pie_params* p,
+                        void* workspace, size_t ws_bytes, double* stats_dev,
+                        void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Amplitude loss L = sum_j || |F_m (P * O_j) F_m^T| - amp_j ||^2 and its
+ * gradient (the derivative through the partial transform that the paper's
+ * gradient view of PIE needs, Sec. 1.1 and the remark after eq. (6)).
+ * Gradients use grad = dL/dRe + i dL/dIm; the subgradient of |u| at 0 is 0.
+ *
+ * amp_loss_forward: loss_dev device double[1] receives L.  saved_u: device
+ *   complex64 [J][m][m] receiving u_j, or NULL.
+ * amp_loss_backward: grad_object device complex64 [H][W] (overwritten with
+ *   grad_scale * dL/dO), grad_probe device complex64 [n][n] (overwritten
+ *   with grad_scale * dL/dP) or NULL.  saved_u from the forward, or NULL to
+ *   recompute the exit waves and their transforms.  workspace as sized by
+ *   amp_loss_workspace_size. */
+pftpie_status amp_loss_workspace_size(pie_scan scan, size_t* bytes);
+pftpie_status amp_loss_forward(pie_scan scan, const void* object, const void* probe,
+                               const float* amp, double* loss_dev, void* saved_u,
+                               void* workspace, size_t ws_bytes, void* stream);
+pftpie_status amp_loss_backward(pie_scan scan, const void* object, const void* probe,
+                                const float* amp, const void* saved_u, float grad_scale,
+                                void* grad_object, void* grad_probe,
+                                void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFTPIE_H */

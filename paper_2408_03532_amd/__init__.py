@@ -1,0 +1,8 @@
+"""MI355X-native batched 2-D partial Fourier transform and PIE sweep.
+
+The computation runs in the HIP library libpftpie.so (C ABI in
+include/pftpie.h); this package only marshals torch tensors into it.
+"""
+
+from ._lib import PftpieError, lib  # noqa: F401
+from .pft import Plan, get_plan, pft2d, pft2d_adj, pft2d_adjoint, pft2d_forward  # noqa: F401

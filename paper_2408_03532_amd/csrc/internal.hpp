@@ -1,0 +1,50 @@
+// Host-side internals shared by the runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pftpie.h"
+#include "twiddle.hpp"
+
+namespace pftpie {
+
+constexpr int kMaxN = 4096;
+constexpr int kMaxM = 128;  // 8 accumulator tiles per axis
+
+// Forward work split for MT = ceil(m/16) output tiles per axis: each wave
+// owns CT column tiles, W = ceil(MT / CT) waves per patch.
+inline int fwd_ct(int mt) { return mt <= 4 ? mt : 2; }
+inline int fwd_waves(int mt) { return (mt + fwd_ct(mt) - 1) / fwd_ct(mt); }
+// Adjoint: waves per patch, each taking every W-th column tile.
+inline int adj_waves(int nb) { return nb >= 4 ? 4 : nb; }
+
+}  // namespace pftpie
+
+struct pftpie_plan_s {
+  int32_t n, m;
+  pftpie_precision prec;
+  int nb, mt;        // ceil(n/16), ceil(m/16)
+  int fa_ctiles;     // column tiles allocated in FA (multiple of the forward CT)
+  int device;
+  float4* fa;        // device FA table
+  float4* ft;        // device FT table
+  size_t fa_bytes, ft_bytes;
+};
+
+namespace pftpie {
+
+// Thread-local error message plumbing.
+pftpie_status fail(pftpie_status s, const std::string& msg);
+pftpie_status hip_fail(hipError_t e, const char* where);
+
+// Launchers (kernels_pft.hip).  Shapes validated by the caller.
+hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch,
+                          hipStream_t st);
+hipError_t launch_adjoint(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch,
+                          hipStream_t st);
+
+}  // namespace pftpie

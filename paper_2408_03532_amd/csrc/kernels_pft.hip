@@ -1,0 +1,126 @@
+// Plain batched partial transform kernels (pft2d_forward / pft2d_adjoint).
+#include "internal.hpp"
+#include "pft_engine.hpp"
+
+namespace pftpie {
+
+// Forward: one workgroup of W waves per patch; wave w owns column tiles
+// [w*CT, w*CT + CT).  Tiles at or beyond MT are computed on the zero rows of
+// the padded table and not stored.
+template <int MT, int CT, bool EXACT>
+__global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_forward(
+    const float2* __restrict__ psi, float2* __restrict__ y, int n, int m, int nb,
+    const float4* __restrict__ fa) {
+  const int64_t b = blockIdx.x;
+  const int w = threadIdx.x >> 6;
+  const int c2t0 = w * CT;
+  PlainSrc<EXACT> src{psi + b * (int64_t)n * n, n};
+  f32x4 Yre[MT][CT], Yim[MT][CT];
+  fwd_wave<MT, CT>(src, nb, fa, c2t0, Yre, Yim);
+  const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
+  float2* out = y + b * (int64_t)m * m;
+#pragma unroll
+  for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c2 = (c2t0 + ct) * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c1 = c1t * 16 + 4 * g + i;
+        if (c1 < m && c2 < m) out[(size_t)c1 * m + c2] = make_float2(Yre[c1t][ct][i], Yim[c1t][ct][i]);
+      }
+    }
+}
+
+// Y source of the plain adjoint (m x m blocks, masked).
+struct CoefSrc {
+  const float2* __restrict__ p;
+  int m;
+  __device__ __forceinline__ c4 load(int row, int col0) const {
+    c4 r;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = col0 + s;
+      r.v[s] = (row < m && col < m) ? p[(size_t)row * m + col] : make_float2(0.f, 0.f);
+    }
+    return r;
+  }
+};
+
+struct StoreSink {
+  float2* __restrict__ out;
+  int n;
+  __device__ __forceinline__ void operator()(int k1t, int k2t, const f32x4& re, const f32x4& im) const {
+    const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
+    const int k2 = k2t * 16 + r16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k1 = k1t * 16 + 4 * g + i;
+      if (k1 < n && k2 < n) out[(size_t)k1 * n + k2] = make_float2(re[i], im[i]);
+    }
+  }
+};
+
+// Adjoint: one workgroup of W waves per patch; wave w takes column tiles
+// w, w + W, ...
+template <int MT>
+__global__ __launch_bounds__(256) void k_adjoint(const float2* __restrict__ y, float2* __restrict__ psi,
+                                                 int n, int m, int nb, const float4* __restrict__ ft) {
+  const int64_t b = blockIdx.x;
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  CoefSrc src{y + b * (int64_t)m * m, m};
+  StoreSink sink{psi + b * (int64_t)n * n, n};
+  for (int kt2 = w; kt2 < nb; kt2 += nw) adj_wave_tile<MT>(src, nb, ft, kt2, sink);
+}
+
+template <int MT>
+static hipError_t fwd_mt(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
+  constexpr int CT = (MT <= 4) ? MT : 2;
+  constexpr int W = (MT + CT - 1) / CT;
+  const bool exact = (p->n % 16 == 0) && ((uintptr_t)psi % 16 == 0);
+  dim3 grid((unsigned)batch), block(64 * W);
+  if (exact)
+    hipLaunchKernelGGL((k_forward<MT, CT, true>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
+  else
+    hipLaunchKernelGGL((k_forward<MT, CT, false>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
+  if (batch == 0) return hipSuccess;
+  switch (p->mt) {
+    case 1: return fwd_mt<1>(p, psi, y, batch, st);
+    case 2: return fwd_mt<2>(p, psi, y, batch, st);
+    case 3: return fwd_mt<3>(p, psi, y, batch, st);
+    case 4: return fwd_mt<4>(p, psi, y, batch, st);
+    case 5: return fwd_mt<5>(p, psi, y, batch, st);
+    case 6: return fwd_mt<6>(p, psi, y, batch, st);
+    case 7: return fwd_mt<7>(p, psi, y, batch, st);
+    case 8: return fwd_mt<8>(p, psi, y, batch, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int MT>
+static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch, hipStream_t st) {
+  dim3 grid((unsigned)batch), block(64 * adj_waves(p->nb));
+  hipLaunchKernelGGL((k_adjoint<MT>), grid, block, 0, st, y, psi, p->n, p->m, p->nb, p->ft);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch, hipStream_t st) {
+  if (batch == 0) return hipSuccess;
+  switch (p->mt) {
+    case 1: return adj_mt<1>(p, y, psi, batch, st);
+    case 2: return adj_mt<2>(p, y, psi, batch, st);
+    case 3: return adj_mt<3>(p, y, psi, batch, st);
+    case 4: return adj_mt<4>(p, y, psi, batch, st);
+    case 5: return adj_mt<5>(p, y, psi, batch, st);
+    case 6: return adj_mt<6>(p, y, psi, batch, st);
+    case 7: return adj_mt<7>(p, y, psi, batch, st);
+    case 8: return adj_mt<8>(p, y, psi, batch, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace pftpie

@@ -1,0 +1,193 @@
+// Wave-level FP32 MFMA engines of the 2-D partial DFT and its adjoint.
+//
+// Forward   Y = F T,       T = psi F^T       (Appendix A, 2-D DFT restricted
+//                                             to the kept window)
+// Adjoint   X = F^H S,     S = Y conj(F)^T   (exact adjoint, no scaling)
+// with F = F_m the m x n partial DFT matrix.  Complex products are four real
+// MFMA products; the negated operand is formed in a register.
+//
+// Forward: one wave owns CT column tiles (16 output columns each) of Y for
+// one patch.  It streams psi in 16-row strips; for each strip it contracts
+// the strip against F^T over all n columns (stage 1, T strip in MFMA
+// accumulators), then immediately contracts F[:, strip] against that T strip
+// into its Y accumulators (stage 2).  The accumulator layout of stage 1 is
+// the B-operand layout of stage 2, so T never leaves registers.
+//
+// Adjoint: one wave owns one 16-column tile of X at a time: stage 1 forms
+// S[:, tile] = Y conj(F)[:, tile] over the m kept columns, stage 2 emits
+// X[row tile, tile] = F^H S for every row tile, handing each finished 16 x 16
+// tile to a sink (plain store, or the PIE scatter).
+//
+// Twiddle tables (built on the host in double, rounded once):
+//   FA block (ct, kb), lane l, entry s = F[16 ct + l%16][16 kb + 4(l/16) + s]
+//   FT block (kt, cb), lane l, entry s = F[16 cb + 4(l/16) + s][16 kt + l%16]
+// zero outside the m x n matrix.  Each block is 2 KB (see load_tw).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace pftpie {
+
+// psi source of the plain transform: patch p, side n.  EXACT: n % 16 == 0
+// and 16-byte aligned base, so every lane chunk is in bounds and aligned.
+template <bool EXACT>
+struct PlainSrc {
+  const float2* __restrict__ p;
+  int n;
+  __device__ __forceinline__ c4 load(int row, int col0) const {
+    c4 r;
+    if (EXACT) {
+      const float4* q = reinterpret_cast<const float4*>(p + (size_t)row * n + col0);
+      float4 a = q[0], b = q[1];
+      r.v[0] = make_float2(a.x, a.y);
+      r.v[1] = make_float2(a.z, a.w);
+      r.v[2] = make_float2(b.x, b.y);
+      r.v[3] = make_float2(b.z, b.w);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        int col = col0 + s;
+        r.v[s] = (row < n && col < n) ? p[(size_t)row * n + col] : make_float2(0.f, 0.f);
+      }
+    }
+    return r;
+  }
+};
+
+// Forward engine.  NB = ceil(n/16) row strips / column blocks.  FA holds
+// ctiles x NB blocks.  c2t0: first column tile this wave owns.
+template <int MT, int CT, class Src>
+__device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* __restrict__ FA,
+                                         int c2t0, f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT]) {
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      Yre[a][b] = zero4();
+      Yim[a][b] = zero4();
+    }
+  for (int strip = 0; strip < NB; ++strip) {
+    const int row = strip * 16 + r16;
+    f32x4 Tre[CT], Tim[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      Tre[ct] = zero4();
+      Tim[ct] = zero4();
+    }
+    c4 a_cur = src.load(row, 4 * g);
+    c4 f_cur[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) f_cur[ct] = load_tw(FA + ((size_t)(c2t0 + ct) * NB) * 128, lane);
+    for (int kb = 0; kb < NB; ++kb) {
+      const int kn = (kb + 1 < NB) ? kb + 1 : kb;  // prefetch next block (clamped)
+      c4 a_nxt = src.load(row, kn * 16 + 4 * g);
+      c4 f_nxt[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        f_nxt[ct] = load_tw(FA + ((size_t)(c2t0 + ct) * NB + kn) * 128, lane);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float ar = a_cur.v[s].x, ai = a_cur.v[s].y, nai = -ai;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          Tre[ct] = mfma4(ar, f_cur[ct].v[s].x, Tre[ct]);
+          Tim[ct] = mfma4(ar, f_cur[ct].v[s].y, Tim[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          Tre[ct] = mfma4(nai, f_cur[ct].v[s].y, Tre[ct]);
+          Tim[ct] = mfma4(ai, f_cur[ct].v[s].x, Tim[ct]);
+        }
+      }
+      a_cur = a_nxt;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) f_cur[ct] = f_nxt[ct];
+    }
+    // stage 2: Y[c1 tile][own tiles] += F[c1 tile, strip] * T[strip, own tiles]
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      c4 fb = load_tw(FA + ((size_t)c1t * NB + strip) * 128, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float fr = fb.v[i].x, fi = fb.v[i].y, nfi = -fi;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          Yre[c1t][ct] = mfma4(fr, Tre[ct][i], Yre[c1t][ct]);
+          Yim[c1t][ct] = mfma4(fr, Tim[ct][i], Yim[c1t][ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          Yre[c1t][ct] = mfma4(nfi, Tim[ct][i], Yre[c1t][ct]);
+          Yim[c1t][ct] = mfma4(fi, Tre[ct][i], Yim[c1t][ct]);
+        }
+      }
+    }
+  }
+}
+
+// Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
+// returns Y[row][col0..col0+3] (zeros outside m x m).  FT holds NB x MT
+// blocks.  sink(k1t, kt2, Xre, Xim) receives each finished tile.
+template <int MT, class YSrc, class Sink>
+__device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const float4* __restrict__ FT,
+                                              int kt2, Sink& sink) {
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+  f32x4 Sre[MT], Sim[MT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a) {
+    Sre[a] = zero4();
+    Sim[a] = zero4();
+  }
+  // stage 1: S[c1][k2 in tile] = sum_c2 Y[c1][c2] conj(F[c2][k2])
+#pragma unroll
+  for (int kb = 0; kb < MT; ++kb) {
+    c4 f = load_tw(FT + ((size_t)kt2 * MT + kb) * 128, lane);
+    c4 y[MT];
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float fr = f.v[s].x, fi = f.v[s].y;
+#pragma unroll
+      for (int c1t = 0; c1t < MT; ++c1t) {
+        Sre[c1t] = mfma4(y[c1t].v[s].x, fr, Sre[c1t]);
+        Sim[c1t] = mfma4(y[c1t].v[s].y, fr, Sim[c1t]);
+      }
+#pragma unroll
+      for (int c1t = 0; c1t < MT; ++c1t) {
+        Sre[c1t] = mfma4(y[c1t].v[s].y, fi, Sre[c1t]);
+        Sim[c1t] = mfma4(-y[c1t].v[s].x, fi, Sim[c1t]);
+      }
+    }
+  }
+  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], two row tiles at a time
+  for (int k1t = 0; k1t < NB; k1t += 2) {
+    const bool two = (k1t + 1 < NB);
+    const int k1b = two ? k1t + 1 : k1t;
+    f32x4 Xre0 = zero4(), Xim0 = zero4(), Xre1 = zero4(), Xim1 = zero4();
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      c4 fa = load_tw(FT + ((size_t)k1t * MT + c1t) * 128, lane);
+      c4 fb = load_tw(FT + ((size_t)k1b * MT + c1t) * 128, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float sr = Sre[c1t][i], si = Sim[c1t][i];
+        Xre0 = mfma4(fa.v[i].x, sr, Xre0);
+        Xim0 = mfma4(fa.v[i].x, si, Xim0);
+        Xre1 = mfma4(fb.v[i].x, sr, Xre1);
+        Xim1 = mfma4(fb.v[i].x, si, Xim1);
+        Xre0 = mfma4(fa.v[i].y, si, Xre0);
+        Xim0 = mfma4(-fa.v[i].y, sr, Xim0);
+        Xre1 = mfma4(fb.v[i].y, si, Xre1);
+        Xim1 = mfma4(-fb.v[i].y, sr, Xim1);
+      }
+    }
+    sink(k1t, kt2, Xre0, Xim0);
+    if (two) sink(k1t + 1, kt2, Xre1, Xim1);
+  }
+}
+
+}  // namespace pftpie

@@ -1,0 +1,151 @@
+// C ABI: plans, validation, error plumbing and dispatch of the partial
+// transform.  Every argument check happens here, on the host, before any
+// work is enqueued.
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pftpie {
+
+static thread_local std::string g_last_error;
+
+pftpie_status fail(pftpie_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+pftpie_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return PFTPIE_E_DEVICE;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+static pftpie_status check_plan(const pftpie_plan_s* p) {
+  if (!p) return fail(PFTPIE_E_INVALID, "plan is NULL");
+  return PFTPIE_OK;
+}
+
+static pftpie_status check_batch_io(const pftpie_plan_s* p, const void* in, size_t in_elems, const void* out,
+                                    size_t out_elems, int64_t batch, const char* what) {
+  if (batch < 0) return fail(PFTPIE_E_INVALID, std::string(what) + ": batch < 0");
+  if (batch > 0x7fffffff) return fail(PFTPIE_E_INVALID, std::string(what) + ": batch exceeds 2^31 - 1");
+  if (batch == 0) return PFTPIE_OK;
+  if (!in || !out) return fail(PFTPIE_E_INVALID, std::string(what) + ": NULL data pointer");
+  if ((uintptr_t)in % 8 || (uintptr_t)out % 8)
+    return fail(PFTPIE_E_INVALID, std::string(what) + ": data pointers must be 8-byte aligned");
+  if (overlaps(in, in_elems * batch * 8, out, out_elems * batch * 8))
+    return fail(PFTPIE_E_INVALID, std::string(what) + ": input and output overlap");
+  if (p->prec != PFTPIE_FP32)
+    return fail(PFTPIE_E_UNSUPPORTED, std::string(what) + ": precision not available for this call");
+  return PFTPIE_OK;
+}
+
+}  // namespace pftpie
+
+using namespace pftpie;
+
+extern "C" {
+
+const char* pftpie_status_string(pftpie_status s) {
+  switch (s) {
+    case PFTPIE_OK: return "ok";
+    case PFTPIE_E_INVALID: return "invalid argument";
+    case PFTPIE_E_UNSUPPORTED: return "unsupported";
+    case PFTPIE_E_NOMEM: return "out of memory";
+    case PFTPIE_E_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* pftpie_last_error(void) { return g_last_error.c_str(); }
+
+pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pftpie_plan* out) {
+  if (!out) return fail(PFTPIE_E_INVALID, "plan_create: out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > kMaxN) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= n <= 4096");
+  if (m < 1 || m > n) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= m <= n");
+  if (prec != PFTPIE_FP32 && prec != PFTPIE_SPLIT_BF16 && prec != PFTPIE_SPLIT_FP16)
+    return fail(PFTPIE_E_INVALID, "plan_create: unknown precision");
+  if (m > kMaxM) return fail(PFTPIE_E_UNSUPPORTED, "plan_create: m > 128 is not supported");
+  pftpie_plan_s* p = new (std::nothrow) pftpie_plan_s();
+  if (!p) return fail(PFTPIE_E_NOMEM, "plan_create: host allocation failed");
+  p->n = n;
+  p->m = m;
+  p->prec = prec;
+  p->nb = ceil16(n);
+  p->mt = ceil16(m);
+  const int ct = fwd_ct(p->mt);
+  p->fa_ctiles = ((p->mt + ct - 1) / ct) * ct;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "plan_create: hipGetDevice");
+  }
+  std::vector<float> fa, ft;
+  build_twiddle_tables(n, m, p->fa_ctiles, fa, ft);
+  p->fa_bytes = fa.size() * sizeof(float);
+  p->ft_bytes = ft.size() * sizeof(float);
+  e = hipMalloc((void**)&p->fa, p->fa_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->ft, p->ft_bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(p->fa);
+    delete p;
+    return fail(PFTPIE_E_NOMEM, std::string("plan_create: hipMalloc: ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(p->fa, fa.data(), p->fa_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->ft, ft.data(), p->ft_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p->fa);
+    (void)hipFree(p->ft);
+    delete p;
+    return hip_fail(e, "plan_create: upload");
+  }
+  *out = p;
+  return PFTPIE_OK;
+}
+
+pftpie_status pftpie_plan_destroy(pftpie_plan plan) {
+  if (!plan) return PFTPIE_OK;
+  (void)hipFree(plan->fa);
+  (void)hipFree(plan->ft);
+  delete plan;
+  return PFTPIE_OK;
+}
+
+pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m, pftpie_precision* prec) {
+  if (pftpie_status s = check_plan(plan)) return s;
+  if (n) *n = plan->n;
+  if (m) *m = plan->m;
+  if (prec) *prec = plan->prec;
+  return PFTPIE_OK;
+}
+
+pftpie_status pft2d_forward(pftpie_plan plan, const void* psi, void* y, int64_t batch, void* stream) {
+  if (pftpie_status s = check_plan(plan)) return s;
+  if (pftpie_status s = check_batch_io(plan, psi, (size_t)plan->n * plan->n, y, (size_t)plan->m * plan->m,
+                                       batch, "pft2d_forward"))
+    return s;
+  hipError_t e = launch_forward(plan, static_cast<const float2*>(psi), static_cast<float2*>(y), batch,
+                                static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pft2d_forward: launch");
+}
+
+pftpie_status pft2d_adjoint(pftpie_plan plan, const void* y, void* psi, int64_t batch, void* stream) {
+  if (pftpie_status s = check_plan(plan)) return s;
+  if (pftpie_status s = check_batch_io(plan, y, (size_t)plan->m * plan->m, psi, (size_t)plan->n * plan->n,
+                                       batch, "pft2d_adjoint"))
+    return s;
+  hipError_t e = launch_adjoint(plan, static_cast<const float2*>(y), static_cast<float2*>(psi), batch,
+                                static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pft2d_adjoint: launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+"""Python binding of the partial transform: plans, forward / adjoint calls on
+torch tensors, and the autograd operator.
+
+The partial transform keeps the centred m x m window of the 2-D DFT of each
+n x n patch (Appendix A; Fig. 2 of the paper): y = F_m psi F_m^T with
+F_m[c, k] = exp(-2 pi i (c - floor(m/2)) k / n).  The adjoint is
+F_m^H y conj(F_m) without normalisation.
+"""
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib
+
+_plans = {}
+_plans_lock = threading.Lock()
+
+
+def _stream_ptr(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _require(t, name, dtype=torch.complex64):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """Twiddle tables of one (n, m, precision) on one device."""
+
+    def __init__(self, n, m, precision="fp32", device=None):
+        if precision not in _lib.PRECISION:
+            raise ValueError(f"precision must be one of {sorted(_lib.PRECISION)}")
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else
+                           torch.device(device).index or 0)
+        self.n, self.m, self.precision, self.device = int(n), int(m), precision, dev
+        h = _lib.c_plan()
+        with torch.cuda.device(dev):
+            _lib.call("pftpie_plan_create", n, m, _lib.PRECISION[precision], ctypes.byref(h))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().pftpie_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, psi, out=None):
+        """psi: complex64 [..., n, n] on this plan's device -> [..., m, m]."""
+        _require(psi, "psi")
+        if psi.shape[-2:] != (self.n, self.n):
+            raise ValueError(f"psi must end in ({self.n}, {self.n}), got {tuple(psi.shape)}")
+        lead = psi.shape[:-2]
+        if out is None:
+            out = torch.empty(lead + (self.m, self.m), dtype=torch.complex64, device=psi.device)
+        _require(out, "out")
+        if out.shape != lead + (self.m, self.m):
+            raise ValueError("out has the wrong shape")
+        batch = psi.numel() // (self.n * self.n)
+        _lib.call("pft2d_forward", self.handle, ctypes.c_void_p(psi.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), batch, _stream_ptr(psi))
+        return out
+
+    def adjoint(self, y, out=None):
+        """y: complex64 [..., m, m] -> F_m^H y conj(F_m), [..., n, n]."""
+        _require(y, "y")
+        if y.shape[-2:] != (self.m, self.m):
+            raise ValueError(f"y must end in ({self.m}, {self.m}), got {tuple(y.shape)}")
+        lead = y.shape[:-2]
+        if out is None:
+            out = torch.empty(lead + (self.n, self.n), dtype=torch.complex64, device=y.device)
+        _require(out, "out")
+        if out.shape != lead + (self.n, self.n):
+            raise ValueError("out has the wrong shape")
+        batch = y.numel() // (self.m * self.m)
+        _lib.call("pft2d_adjoint", self.handle, ctypes.c_void_p(y.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), batch, _stream_ptr(y))
+        return out
+
+
+def get_plan(n, m, precision="fp32", device=None):
+    """Cached plan for (device, n, m, precision)."""
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    key = (dev, int(n), int(m), precision)
+    with _plans_lock:
+        p = _plans.get(key)
+        if p is None:
+            p = Plan(n, m, precision, device=torch.device("cuda", dev))
+            _plans[key] = p
+        return p
+
+
+def pft2d_forward(psi, m, precision="fp32", out=None):
+    """Centred m x m partial DFT of every trailing n x n patch of psi."""
+    return get_plan(psi.shape[-1], m, precision, psi.device).forward(psi.contiguous(), out)
+
+
+def pft2d_adjoint(y, n, precision="fp32", out=None):
+    """Adjoint F_m^H y conj(F_m) of every trailing m x m block of y."""
+    return get_plan(n, y.shape[-1], precision, y.device).adjoint(y.contiguous(), out)
+
+
+class _PFT2D(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, psi, m, precision):
+        ctx.n, ctx.precision = psi.shape[-1], precision
+        return pft2d_forward(psi, m, precision)
+
+    @staticmethod
+    def backward(ctx, gy):
+        # y = A psi is complex-linear: the gradient is A^H applied to gy
+        return pft2d_adjoint(gy.contiguous(), ctx.n, ctx.precision), None, None
+
+
+class _PFT2DAdjoint(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y, n, precision):
+        ctx.m, ctx.precision = y.shape[-1], precision
+        return pft2d_adjoint(y, n, precision)
+
+    @staticmethod
+    def backward(ctx, gx):
+        return pft2d_forward(gx.contiguous(), ctx.m, ctx.precision), None, None
+
+
+def pft2d(psi, m, precision="fp32"):
+    """Differentiable partial transform (backward = adjoint)."""
+    return _PFT2D.apply(psi, m, precision)
+
+
+def pft2d_adj(y, n, precision="fp32"):
+    """Differentiable adjoint (backward = forward)."""
+    return _PFT2DAdjoint.apply(y, n, precision)
