@@ -16,9 +16,14 @@ constexpr int kMaxN = 4096;
 constexpr int kMaxM = 128;  // 8 accumulator tiles per axis
 
 // Forward work split for MT = ceil(m/16) output tiles per axis: each wave
-// owns CT column tiles, W = ceil(MT / CT) waves per patch.
-inline int fwd_ct(int mt) { return mt <= 4 ? mt : 2; }
-inline int fwd_waves(int mt) { return (mt + fwd_ct(mt) - 1) / fwd_ct(mt); }
+// owns CT column tiles, W = ceil(MT / CT) waves per patch.  Valid CT: 1, 2
+// (MT >= 2), 3 (MT == 3), 4 (MT == 4).
+inline int fwd_ct_default(int mt) { return mt <= 2 ? mt : 2; }
+inline bool fwd_ct_valid(int mt, int ct) {
+  return ct == 1 || (ct == 2 && mt >= 2) || (ct == 3 && mt == 3) || (ct == 4 && mt == 4);
+}
+// Column tiles allocated in the FA table: enough for every valid split.
+inline int fa_ctiles_for(int mt) { return ((mt + 3) / 4) * 4; }
 // Adjoint: waves per patch, each taking every W-th column tile.
 inline int adj_waves(int nb) { return nb >= 4 ? 4 : nb; }
 
@@ -28,7 +33,8 @@ struct pftpie_plan_s {
   int32_t n, m;
   pftpie_precision prec;
   int nb, mt;        // ceil(n/16), ceil(m/16)
-  int fa_ctiles;     // column tiles allocated in FA (multiple of the forward CT)
+  int fa_ctiles;     // column tiles allocated in FA (covers every forward split)
+  int fwd_ct;        // forward column tiles per wave
   int device;
   float4* fa;        // device FA table
   float4* ft;        // device FT table

@@ -73,9 +73,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const float2* __restrict__ y, f
   for (int kt2 = w; kt2 < nb; kt2 += nw) adj_wave_tile<MT>(src, nb, ft, kt2, sink);
 }
 
-template <int MT>
-static hipError_t fwd_mt(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
-  constexpr int CT = (MT <= 4) ? MT : 2;
+template <int MT, int CT>
+static hipError_t fwd_mt_ct(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
   constexpr int W = (MT + CT - 1) / CT;
   const bool exact = (p->n % 16 == 0) && ((uintptr_t)psi % 16 == 0);
   dim3 grid((unsigned)batch), block(64 * W);
@@ -84,6 +83,18 @@ static hipError_t fwd_mt(const pftpie_plan_s* p, const float2* psi, float2* y, i
   else
     hipLaunchKernelGGL((k_forward<MT, CT, false>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
   return hipGetLastError();
+}
+
+template <int MT>
+static hipError_t fwd_mt(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
+  // column tiles per wave: 4 only while the Y accumulators stay <= 128 registers
+  switch (p->fwd_ct) {
+    case 1: return fwd_mt_ct<MT, 1>(p, psi, y, batch, st);
+    case 2: if constexpr (MT >= 2) return fwd_mt_ct<MT, 2>(p, psi, y, batch, st); break;
+    case 4: if constexpr (MT >= 4 && MT <= 4) return fwd_mt_ct<MT, 4>(p, psi, y, batch, st); break;
+    case 3: if constexpr (MT == 3) return fwd_mt_ct<MT, 3>(p, psi, y, batch, st); break;
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {

@@ -76,35 +76,41 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* _
       Tre[ct] = zero4();
       Tim[ct] = zero4();
     }
-    c4 a_cur = src.load(row, 4 * g);
-    c4 f_cur[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) f_cur[ct] = load_tw(FA + ((size_t)(c2t0 + ct) * NB) * 128, lane);
-    for (int kb = 0; kb < NB; ++kb) {
-      const int kn = (kb + 1 < NB) ? kb + 1 : kb;  // prefetch next block (clamped)
-      c4 a_nxt = src.load(row, kn * 16 + 4 * g);
-      c4 f_nxt[CT];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        f_nxt[ct] = load_tw(FA + ((size_t)(c2t0 + ct) * NB + kn) * 128, lane);
+    // stage 1 over column blocks, two register sets in ping-pong so the loads
+    // of one block are in flight while the other block's products issue
+    auto stage1 = [&](const c4& a, const c4(&f)[CT]) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const float ar = a_cur.v[s].x, ai = a_cur.v[s].y, nai = -ai;
+        const float ar = a.v[s].x, ai = a.v[s].y, nai = -ai;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-          Tre[ct] = mfma4(ar, f_cur[ct].v[s].x, Tre[ct]);
-          Tim[ct] = mfma4(ar, f_cur[ct].v[s].y, Tim[ct]);
+          Tre[ct] = mfma4(ar, f[ct].v[s].x, Tre[ct]);
+          Tim[ct] = mfma4(ar, f[ct].v[s].y, Tim[ct]);
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-          Tre[ct] = mfma4(nai, f_cur[ct].v[s].y, Tre[ct]);
-          Tim[ct] = mfma4(ai, f_cur[ct].v[s].x, Tim[ct]);
+          Tre[ct] = mfma4(nai, f[ct].v[s].y, Tre[ct]);
+          Tim[ct] = mfma4(ai, f[ct].v[s].x, Tim[ct]);
         }
       }
-      a_cur = a_nxt;
+    };
+    auto fetch = [&](int kb, c4& a, c4(&f)[CT]) {
+      a = src.load(row, kb * 16 + 4 * g);
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) f_cur[ct] = f_nxt[ct];
+      for (int ct = 0; ct < CT; ++ct) f[ct] = load_tw(FA + ((size_t)(c2t0 + ct) * NB + kb) * 128, lane);
+    };
+    c4 a0, a1, f0[CT], f1[CT];
+    fetch(0, a0, f0);
+    int kb = 0;
+    for (; kb + 1 < NB; kb += 2) {
+      fetch(kb + 1, a1, f1);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a0, f0);
+      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a1, f1);
     }
+    if (kb < NB) stage1(a0, f0);
     // stage 2: Y[c1 tile][own tiles] += F[c1 tile, strip] * T[strip, own tiles]
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
@@ -142,12 +148,7 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const fl
     Sim[a] = zero4();
   }
   // stage 1: S[c1][k2 in tile] = sum_c2 Y[c1][c2] conj(F[c2][k2])
-#pragma unroll
-  for (int kb = 0; kb < MT; ++kb) {
-    c4 f = load_tw(FT + ((size_t)kt2 * MT + kb) * 128, lane);
-    c4 y[MT];
-#pragma unroll
-    for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+  auto stage1 = [&](const c4& f, const c4(&y)[MT]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const float fr = f.v[s].x, fi = f.v[s].y;
@@ -162,29 +163,65 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const fl
         Sim[c1t] = mfma4(-y[c1t].v[s].x, fi, Sim[c1t]);
       }
     }
+  };
+  auto fetch1 = [&](int kb, c4& f, c4(&y)[MT]) {
+    f = load_tw(FT + ((size_t)kt2 * MT + kb) * 128, lane);
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+  };
+  if constexpr (MT <= 4) {
+    c4 f[2], y[2][MT];
+    fetch1(0, f[0], y[0]);
+#pragma unroll
+    for (int kb = 0; kb < MT; ++kb) {
+      if (kb + 1 < MT) fetch1(kb + 1, f[(kb + 1) & 1], y[(kb + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(f[kb & 1], y[kb & 1]);
+    }
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < MT; ++kb) {
+      c4 f, y[MT];
+      fetch1(kb, f, y);
+      stage1(f, y);
+    }
   }
-  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], two row tiles at a time
+  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], two row tiles at a
+  // time; the twiddle blocks of the next step are fetched while the current
+  // step's products issue (ping-pong buffers, no register copies).
+  auto fetch2 = [&](int k1t, int c1t, c4& fa, c4& fb) {
+    const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
+    fa = load_tw(FT + ((size_t)k1t * MT + c1t) * 128, lane);
+    fb = load_tw(FT + ((size_t)k1b * MT + c1t) * 128, lane);
+  };
+  c4 fa[2], fb[2];
+  fetch2(0, 0, fa[0], fb[0]);
   for (int k1t = 0; k1t < NB; k1t += 2) {
     const bool two = (k1t + 1 < NB);
-    const int k1b = two ? k1t + 1 : k1t;
+    const int k1n = (k1t + 2 < NB) ? k1t + 2 : k1t;
     f32x4 Xre0 = zero4(), Xim0 = zero4(), Xre1 = zero4(), Xim1 = zero4();
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
-      c4 fa = load_tw(FT + ((size_t)k1t * MT + c1t) * 128, lane);
-      c4 fb = load_tw(FT + ((size_t)k1b * MT + c1t) * 128, lane);
+      const int cur = c1t & 1;
+      if (c1t + 1 < MT)
+        fetch2(k1t, c1t + 1, fa[cur ^ 1], fb[cur ^ 1]);
+      else if ((MT & 1) == 0)
+        fetch2(k1n, 0, fa[cur ^ 1], fb[cur ^ 1]);  // cur ^ 1 == 0 here
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float sr = Sre[c1t][i], si = Sim[c1t][i];
-        Xre0 = mfma4(fa.v[i].x, sr, Xre0);
-        Xim0 = mfma4(fa.v[i].x, si, Xim0);
-        Xre1 = mfma4(fb.v[i].x, sr, Xre1);
-        Xim1 = mfma4(fb.v[i].x, si, Xim1);
-        Xre0 = mfma4(fa.v[i].y, si, Xre0);
-        Xim0 = mfma4(-fa.v[i].y, sr, Xim0);
-        Xre1 = mfma4(fb.v[i].y, si, Xre1);
-        Xim1 = mfma4(-fb.v[i].y, sr, Xim1);
+        Xre0 = mfma4(fa[cur].v[i].x, sr, Xre0);
+        Xim0 = mfma4(fa[cur].v[i].x, si, Xim0);
+        Xre1 = mfma4(fb[cur].v[i].x, sr, Xre1);
+        Xim1 = mfma4(fb[cur].v[i].x, si, Xim1);
+        Xre0 = mfma4(fa[cur].v[i].y, si, Xre0);
+        Xim0 = mfma4(-fa[cur].v[i].y, sr, Xim0);
+        Xre1 = mfma4(fb[cur].v[i].y, si, Xre1);
+        Xim1 = mfma4(-fb[cur].v[i].y, sr, Xim1);
       }
     }
+    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fa[0], fb[0]);
     sink(k1t, kt2, Xre0, Xim0);
     if (two) sink(k1t + 1, kt2, Xre1, Xim1);
   }

@@ -1,6 +1,7 @@
 // C ABI: plans, validation, error plumbing and dispatch of the partial
 // transform.  Every argument check happens here, on the host, before any
 // work is enqueued.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -82,8 +83,12 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
   p->prec = prec;
   p->nb = ceil16(n);
   p->mt = ceil16(m);
-  const int ct = fwd_ct(p->mt);
-  p->fa_ctiles = ((p->mt + ct - 1) / ct) * ct;
+  p->fa_ctiles = fa_ctiles_for(p->mt);
+  p->fwd_ct = fwd_ct_default(p->mt);
+  if (const char* env = std::getenv("PFTPIE_FWD_CT")) {  // tuning override
+    const int ct = std::atoi(env);
+    if (fwd_ct_valid(p->mt, ct)) p->fwd_ct = ct;
+  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;

@@ -1,0 +1,68 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and rejects invalid arguments on the host before touching
+the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2408_03532_amd as pk
+from paper_2408_03532_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pftpie.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^(?:const\s+char\s*\*|pftpie_status)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = declared()
+    assert len(names) >= 15
+    L = pk.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_status_strings():
+    L = pk.lib()
+    assert L.pftpie_status_string(0) == b"ok"
+    assert L.pftpie_status_string(1) == b"invalid argument"
+    assert L.pftpie_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("n,m,prec,msg", [(0, 1, 0, b"n <= 4096"), (8, 9, 0, b"m <= n"), (8, 0, 0, b"m <= n"),
+                                          (5000, 4, 0, b"n <= 4096"), (8, 4, 7, b"unknown precision")])
+def test_plan_create_rejects_bad_sizes_before_the_device(n, m, prec, msg):
+    L = pk.lib()
+    h = ctypes.c_void_p(123)
+    assert L.pftpie_plan_create(n, m, prec, ctypes.byref(h)) == 1
+    assert h.value is None
+    assert msg in L.pftpie_last_error()
+
+
+def test_plan_create_large_window_is_unsupported():
+    L = pk.lib()
+    h = ctypes.c_void_p()
+    assert L.pftpie_plan_create(512, 256, 0, ctypes.byref(h)) == 2
+
+
+def test_null_handles_are_invalid_not_fatal():
+    L = pk.lib()
+    assert L.pft2d_forward(None, None, None, 1, None) == 1
+    assert L.pft2d_adjoint(None, None, None, 1, None) == 1
+    assert L.pftpie_plan_destroy(None) == 0
+    assert L.pftpie_plan_create(8, 4, 0, None) == 1
+
+
+def test_python_layer_reports_missing_device_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(Exception):
+        pk.Plan(32, 16)
