@@ -170,6 +170,14 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
                         void* workspace, size_t ws_bytes, double* stats_dev,
                         void* stream);
 
+/* Data cropping of Algorithm 3 (Sec. 3.2): amp[j] = sqrt(centred m x m crop
+ * of intensity[j]).  intensity: device float32 [J][n][n] in fftshift layout
+ * (zero frequency at (floor(n/2), floor(n/2))), non-negative; amp: device
+ * float32 [J][m][m], the layout pie_sweep and the loss calls take.  Rows and
+ * columns floor(n/2) - floor(m/2) .. + m - 1 are kept.  1 <= m <= n. */
+pftpie_status pie_crop_amplitudes(const float* intensity, int32_t J, int32_t n, int32_t m,
+                                  float* amp, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Amplitude loss L = sum_j || |F_m (P * O_j) F_m^T| - amp_j ||^2 and its
  * gradient (the derivative through the partial transform that the paper's

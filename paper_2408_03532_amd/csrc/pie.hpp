@@ -1,0 +1,54 @@
+// Kernel-side argument block of the PIE sweep and the amplitude loss, and
+// the scan object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace pftpie {
+
+constexpr int kModeDirect = 0;  // norm 0, probe fixed: scatter beta conj(P) dpsi into O
+constexpr int kModeAccum = 1;   // accumulate numO (D, numP, E), then apply
+
+struct PieArgs {
+  // problem
+  int n, m, nb, mt, J, H, W;
+  int bb_r0, bb_c0, bb_h, bb_w;  // bounding box of all windows
+  const int2* pos;               // [J] (row, col)
+  const int32_t* order;          // [J] or null
+  const float4* fa;
+  const float4* ft;
+  float inv_n2;
+  // parameters
+  int mode, norm, probe_step;
+  float beta, gamma;
+  double alpha;
+  // data
+  float2* O;        // [H][W]
+  float2* P;        // [n][n]
+  const float* amp; // [J][m][m]
+  // workspace
+  float2* R;        // [batch][m][m] residuals
+  double* phi_part; // [J][4]
+  float2* O0;       // [H][W] object at sweep start
+  float2* numO;     // [H][W] or null
+  double* D;        // [H][W] or null
+  float2* numP;     // [n][n] or null
+  double* E;        // [n][n] or null
+  double* maxes;    // [2]
+  double* stats;    // [4]
+};
+
+hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
+hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);
+
+}  // namespace pftpie
+
+struct pie_scan_s {
+  pftpie_plan_s* plan;
+  int32_t J, H, W;
+  int bb_r0, bb_c0, bb_h, bb_w;
+  int2* pos;  // device [J]
+};

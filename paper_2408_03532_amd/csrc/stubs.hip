@@ -13,18 +13,6 @@ pftpie_status pftpie_group_destroy(pft2d_group) { return PFTPIE_OK; }
 pftpie_status pft2d_group_run(pft2d_group, const void*, void*, void*) {
   return fail(PFTPIE_E_UNSUPPORTED, "grouped transform not built yet");
 }
-pftpie_status pie_scan_create(pftpie_plan, const int32_t*, int32_t, int32_t, int32_t, pie_scan* out) {
-  if (out) *out = nullptr;
-  return fail(PFTPIE_E_UNSUPPORTED, "pie not built yet");
-}
-pftpie_status pie_scan_destroy(pie_scan) { return PFTPIE_OK; }
-pftpie_status pie_workspace_size(pie_scan, const pie_params*, size_t*) {
-  return fail(PFTPIE_E_UNSUPPORTED, "pie not built yet");
-}
-pftpie_status pie_sweep(pie_scan, void*, void*, const float*, const int32_t*, const pie_params*, void*, size_t,
-                        double*, void*) {
-  return fail(PFTPIE_E_UNSUPPORTED, "pie not built yet");
-}
 pftpie_status amp_loss_workspace_size(pie_scan, size_t*) { return fail(PFTPIE_E_UNSUPPORTED, "loss not built yet"); }
 pftpie_status amp_loss_forward(pie_scan, const void*, const void*, const float*, double*, void*, void*, size_t,
                                void*) {
