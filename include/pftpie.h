@@ -187,16 +187,18 @@ pftpie_status pie_crop_amplitudes(const float* intensity, int32_t J, int32_t n, 
  * amp_loss_forward: loss_dev device double[1] receives L.  saved_u: device
  *   complex64 [J][m][m] receiving u_j, or NULL.
  * amp_loss_backward: grad_object device complex64 [H][W] (overwritten with
- *   grad_scale * dL/dO), grad_probe device complex64 [n][n] (overwritten
- *   with grad_scale * dL/dP) or NULL.  saved_u from the forward, or NULL to
- *   recompute the exit waves and their transforms.  workspace as sized by
- *   amp_loss_workspace_size. */
+ *   scale * dL/dO), grad_probe device complex64 [n][n] (overwritten with
+ *   scale * dL/dP) or NULL, where scale = *grad_scale_dev (device double) or
+ *   1 when grad_scale_dev is NULL.  saved_u: the u_j written by
+ *   amp_loss_forward, or NULL to recompute them (one more forward
+ *   transform).  The exit waves themselves are never stored.  workspace as
+ *   sized by amp_loss_workspace_size (256-byte aligned). */
 pftpie_status amp_loss_workspace_size(pie_scan scan, size_t* bytes);
 pftpie_status amp_loss_forward(pie_scan scan, const void* object, const void* probe,
                                const float* amp, double* loss_dev, void* saved_u,
                                void* workspace, size_t ws_bytes, void* stream);
 pftpie_status amp_loss_backward(pie_scan scan, const void* object, const void* probe,
-                                const float* amp, const void* saved_u, float grad_scale,
+                                const float* amp, const void* saved_u, const double* grad_scale_dev,
                                 void* grad_object, void* grad_probe,
                                 void* workspace, size_t ws_bytes, void* stream);
 

@@ -53,7 +53,7 @@ SIGNATURES = {
     "pie_crop_amplitudes": (i32, [vp, i32, i32, i32, vp, vp]),
     "amp_loss_workspace_size": (i32, [c_scan, ctypes.POINTER(sz)]),
     "amp_loss_forward": (i32, [c_scan, vp, vp, vp, vp, vp, vp, sz, vp]),
-    "amp_loss_backward": (i32, [c_scan, vp, vp, vp, vp, f32, vp, vp, vp, sz, vp]),
+    "amp_loss_backward": (i32, [c_scan, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
 }
 
 _lib = None

@@ -30,29 +30,6 @@ __device__ __forceinline__ int pos_index(const int32_t* __restrict__ order, int 
   return ok ? j : 0;
 }
 
-// psi[k1][k2] = P[k1][k2] * O[r + k1][c + k2]; zero outside the n x n patch.
-template <bool EXACT>
-struct GatherSrc {
-  const float2* __restrict__ O;
-  const float2* __restrict__ P;
-  int W, n, r, c;
-  __device__ __forceinline__ c4 load(int row, int col0) const {
-    c4 v;
-    const float2* orow = O + (size_t)(r + row) * W + c + col0;
-    const float2* prow = P + (size_t)row * n + col0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int col = col0 + s;
-      if (EXACT || (row < n && col < n)) {
-        v.v[s] = cmul(prow[s], orow[s]);
-      } else {
-        v.v[s] = make_float2(0.f, 0.f);
-      }
-    }
-    return v;
-  }
-};
-
 template <int MT, int CT, bool EXACT>
 __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieArgs a, int c0) {
   const int q = blockIdx.x;

@@ -1,0 +1,28 @@
+// Kernel argument block of the amplitude loss and its gradient.
+#pragma once
+
+#include "pie.hpp"
+
+namespace pftpie {
+
+struct LossArgs {
+  int n, m, nb, mt, J, H, W;
+  const int2* pos;
+  const float4* fa;
+  const float4* ft;
+  const float2* O;
+  const float2* P;
+  const float* amp;
+  float2* U;              // forward: where u_j are written (or null)
+  const float2* Uc;       // backward: where u_j are read
+  double* part;           // [J][4] partial losses
+  double* loss;           // [1] or null
+  const double* scale_dev;
+  float2* gO;
+  float2* gP;
+};
+
+hipError_t launch_loss_forward(const LossArgs& a, hipStream_t st);
+hipError_t launch_loss_backward(const LossArgs& a, bool recompute, hipStream_t st);
+
+}  // namespace pftpie

@@ -6,6 +6,9 @@
 #include <stdint.h>
 
 #include "internal.hpp"
+#ifdef __HIPCC__
+#include "device_common.hpp"
+#endif
 
 namespace pftpie {
 
@@ -43,6 +46,32 @@ struct PieArgs {
 
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);
+
+#ifdef __HIPCC__
+// psi[k1][k2] = P[k1][k2] * O[r + k1][c + k2]; zero outside the n x n patch.
+template <bool EXACT>
+struct GatherSrc {
+  const float2* __restrict__ O;
+  const float2* __restrict__ P;
+  int W, n, r, c;
+  __device__ __forceinline__ c4 load(int row, int col0) const {
+    c4 v;
+    const float2* orow = O + (size_t)(r + row) * W + c + col0;
+    const float2* prow = P + (size_t)row * n + col0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = col0 + s;
+      if (EXACT || (row < n && col < n)) {
+        v.v[s] = cmul(prow[s], orow[s]);
+      } else {
+        v.v[s] = make_float2(0.f, 0.f);
+      }
+    }
+    return v;
+  }
+};
+
+#endif
 
 }  // namespace pftpie
 

@@ -13,13 +13,4 @@ pftpie_status pftpie_group_destroy(pft2d_group) { return PFTPIE_OK; }
 pftpie_status pft2d_group_run(pft2d_group, const void*, void*, void*) {
   return fail(PFTPIE_E_UNSUPPORTED, "grouped transform not built yet");
 }
-pftpie_status amp_loss_workspace_size(pie_scan, size_t*) { return fail(PFTPIE_E_UNSUPPORTED, "loss not built yet"); }
-pftpie_status amp_loss_forward(pie_scan, const void*, const void*, const float*, double*, void*, void*, size_t,
-                               void*) {
-  return fail(PFTPIE_E_UNSUPPORTED, "loss not built yet");
-}
-pftpie_status amp_loss_backward(pie_scan, const void*, const void*, const float*, const void*, float, void*, void*,
-                                void*, size_t, void*) {
-  return fail(PFTPIE_E_UNSUPPORTED, "loss not built yet");
-}
 }
