@@ -64,3 +64,68 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 }  // namespace pftpie
+
+namespace pftpie {
+
+// ---------------------------------------------------------------------------
+// Split 16-bit operands (v_mfma_f32_16x16x32_{bf16,f16}): a lane supplies 8
+// 16-bit values per operand; lane group g = l / 16 holds K-slots
+// 8g .. 8g+7 for A and B alike.  The kernels pack 4 complex values per lane
+// group as (re, im) pairs in those slots, the same complex index mapping as
+// the FP32 engine (k = 16 block + 4 g + s).
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+struct PrecBF16 {
+  typedef __bf16 T;
+  typedef bf16x8 V;
+  static __device__ __forceinline__ f32x4 mfma(V a, V b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+struct PrecF16 {
+  typedef _Float16 T;
+  typedef f16x8 V;
+  static __device__ __forceinline__ f32x4 mfma(V a, V b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// hi = RNE(x), lo = RNE(x - hi) for 8 floats (x - hi is exact in float).
+template <class PR>
+__device__ __forceinline__ void split8(const float (&x)[8], typename PR::V& hi, typename PR::V& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const typename PR::T h = (typename PR::T)x[e];
+    hi[e] = h;
+    lo[e] = (typename PR::T)(x[e] - (float)h);
+  }
+}
+
+// Split twiddle block: plane 0 (1 KB) = hi parts, plane 1 = lo parts, each
+// 8 x 16-bit per lane: (re_s, im_s) for s = 0..3.
+template <class PR>
+struct TwS {
+  typename PR::V h, l;
+};
+template <class PR>
+__device__ __forceinline__ TwS<PR> load_tws(const void* __restrict__ blk, int lane) {
+  const typename PR::V* p = reinterpret_cast<const typename PR::V*>(blk);
+  TwS<PR> r;
+  r.h = p[lane];
+  r.l = p[64 + lane];
+  return r;
+}
+
+// acc += a * b with split operands: hi*hi + hi*lo + lo*hi
+template <class PR>
+__device__ __forceinline__ f32x4 mfma3(const typename PR::V& ah, const typename PR::V& al, const TwS<PR>& b,
+                                       f32x4 c) {
+  c = PR::mfma(ah, b.h, c);
+  c = PR::mfma(ah, b.l, c);
+  c = PR::mfma(al, b.h, c);
+  return c;
+}
+
+}  // namespace pftpie

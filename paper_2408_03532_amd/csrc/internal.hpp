@@ -36,8 +36,8 @@ struct pftpie_plan_s {
   int fa_ctiles;     // column tiles allocated in FA (covers every forward split)
   int fwd_ct;        // forward column tiles per wave
   int device;
-  float4* fa;        // device FA table
-  float4* ft;        // device FT table
+  void* fa;          // device FA table (float4 blocks, or split 16-bit blocks)
+  void* ft;          // device FT table
   size_t fa_bytes, ft_bytes;
 };
 

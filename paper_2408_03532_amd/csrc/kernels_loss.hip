@@ -11,11 +11,11 @@
 //                  the exit waves are never stored.
 #include "internal.hpp"
 #include "loss.hpp"
-#include "pft_engine.hpp"
+#include "pft_split.hpp"
 
 namespace pftpie {
 
-template <int MT, int CT, bool EXACT>
+template <class PR, int MT, int CT, bool EXACT>
 __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(LossArgs a) {
   const int j = blockIdx.x;
   const int w = threadIdx.x >> 6;
@@ -23,8 +23,8 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(Loss
   const int2 ps = a.pos[j];
   GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_wave<MT, CT>(src, a.nb, a.fa, c2t0, Yre, Yim);
-  const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
+  fwd_engine<PR, MT, CT>(src, a.nb, a.fa, c2t0, Yre, Yim);
+  const int lane = lane_id();
   const int m = a.m;
   const float* amp = a.amp + (size_t)j * m * m;
   float2* u = a.U ? a.U + (size_t)j * m * m : nullptr;
@@ -33,10 +33,10 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(Loss
   for (int c1t = 0; c1t < MT; ++c1t)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int c2 = (c2t0 + ct) * 16 + r16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int c1 = c1t * 16 + 4 * g + i;
+        const int2 rc = tile_rc<Orient<PR>::TR>(c1t, c2t0 + ct, i, lane);
+        const int c1 = rc.x, c2 = rc.y;
         if (c1 < m && c2 < m) {
           const float ur = Yre[c1t][ct][i], ui = Yim[c1t][ct][i];
           if (u) u[(size_t)c1 * m + c2] = make_float2(ur, ui);
@@ -80,12 +80,13 @@ struct GradSink {
   float2* __restrict__ gP;
   int n, W, r, c;
   float scale;
-  __device__ __forceinline__ void operator()(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
-    const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
-    const int k2 = k2t * 16 + r16;
+  template <bool TR>
+  __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
+    const int lane = lane_id();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int k1 = k1t * 16 + 4 * g + i;
+      const int2 rc = tile_rc<TR>(k1t, k2t, i, lane);
+      const int k1 = rc.x, k2 = rc.y;
       if (k1 < n && k2 < n) {
         const float2 R = make_float2(scale * xre[i], scale * xim[i]);
         const size_t pi = (size_t)k1 * n + k2;
@@ -103,7 +104,7 @@ struct GradSink {
   }
 };
 
-template <int MT>
+template <class PR, int MT>
 __global__ __launch_bounds__(256) void k_loss_adjoint(LossArgs a) {
   const int j = blockIdx.x;
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_loss_adjoint(LossArgs a) {
   GradSrc src{a.Uc + (size_t)j * mm, a.amp + (size_t)j * mm, a.m};
   const float scale = a.scale_dev ? (float)a.scale_dev[0] : 1.f;
   GradSink sink{a.O, a.P, a.gO, a.gP, a.n, a.W, ps.x, ps.y, scale};
-  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_wave_tile<MT>(src, a.nb, a.ft, kt2, sink);
+  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, a.ft, kt2, sink);
 }
 
 __global__ __launch_bounds__(256) void k_loss_reduce(LossArgs a) {
@@ -146,14 +147,35 @@ __global__ __launch_bounds__(256) void k_loss_clear_parts(LossArgs a) {
     a.part[t] = 0.0;
 }
 
-template <int MT>
-static void fwd_mt(const LossArgs& a, hipStream_t st) {
+template <class PR, int MT>
+static void fwd_prec(const LossArgs& a, hipStream_t st) {
   constexpr int CT = (MT <= 2) ? MT : 2;
   constexpr int W = (MT + CT - 1) / CT;
   if (a.n % 16 == 0)
-    hipLaunchKernelGGL((k_loss_forward<MT, CT, true>), dim3(a.J), dim3(64 * W), 0, st, a);
+    hipLaunchKernelGGL((k_loss_forward<PR, MT, CT, true>), dim3(a.J), dim3(64 * W), 0, st, a);
   else
-    hipLaunchKernelGGL((k_loss_forward<MT, CT, false>), dim3(a.J), dim3(64 * W), 0, st, a);
+    hipLaunchKernelGGL((k_loss_forward<PR, MT, CT, false>), dim3(a.J), dim3(64 * W), 0, st, a);
+}
+
+template <int MT>
+static void fwd_mt(const LossArgs& a, hipStream_t st) {
+  if (a.prec == PFTPIE_SPLIT_BF16)
+    fwd_prec<PrecBF16, MT>(a, st);
+  else if (a.prec == PFTPIE_SPLIT_FP16)
+    fwd_prec<PrecF16, MT>(a, st);
+  else
+    fwd_prec<PrecF32, MT>(a, st);
+}
+
+template <int MT>
+static void adj_mt(const LossArgs& a, hipStream_t st) {
+  dim3 grid(a.J), block(64 * adj_waves(a.nb));
+  if (a.prec == PFTPIE_SPLIT_BF16)
+    hipLaunchKernelGGL((k_loss_adjoint<PrecBF16, MT>), grid, block, 0, st, a);
+  else if (a.prec == PFTPIE_SPLIT_FP16)
+    hipLaunchKernelGGL((k_loss_adjoint<PrecF16, MT>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_loss_adjoint<PrecF32, MT>), grid, block, 0, st, a);
 }
 
 static hipError_t fwd_dispatch(const LossArgs& a, hipStream_t st) {
@@ -188,16 +210,15 @@ hipError_t launch_loss_backward(const LossArgs& a, bool recompute, hipStream_t s
   hipLaunchKernelGGL(k_loss_clear, dim3(blocks_for((size_t)a.H * a.W)), dim3(256), 0, st, a);
   if (recompute)
     if (hipError_t e = fwd_dispatch(a, st)) return e;
-  dim3 grid(a.J), block(64 * adj_waves(a.nb));
   switch (a.mt) {
-    case 1: hipLaunchKernelGGL((k_loss_adjoint<1>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_loss_adjoint<2>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_loss_adjoint<3>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_loss_adjoint<4>), grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_loss_adjoint<5>), grid, block, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((k_loss_adjoint<6>), grid, block, 0, st, a); break;
-    case 7: hipLaunchKernelGGL((k_loss_adjoint<7>), grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_loss_adjoint<8>), grid, block, 0, st, a); break;
+    case 1: adj_mt<1>(a, st); break;
+    case 2: adj_mt<2>(a, st); break;
+    case 3: adj_mt<3>(a, st); break;
+    case 4: adj_mt<4>(a, st); break;
+    case 5: adj_mt<5>(a, st); break;
+    case 6: adj_mt<6>(a, st); break;
+    case 7: adj_mt<7>(a, st); break;
+    case 8: adj_mt<8>(a, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,33 +1,32 @@
 // Plain batched partial transform kernels (pft2d_forward / pft2d_adjoint).
 #include "internal.hpp"
-#include "pft_engine.hpp"
+#include "pft_split.hpp"
 
 namespace pftpie {
 
 // Forward: one workgroup of W waves per patch; wave w owns column tiles
 // [w*CT, w*CT + CT).  Tiles at or beyond MT are computed on the zero rows of
 // the padded table and not stored.
-template <int MT, int CT, bool EXACT>
+template <class PR, int MT, int CT, bool EXACT>
 __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_forward(
     const float2* __restrict__ psi, float2* __restrict__ y, int n, int m, int nb,
-    const float4* __restrict__ fa) {
+    const void* __restrict__ fa) {
   const int64_t b = blockIdx.x;
   const int w = threadIdx.x >> 6;
   const int c2t0 = w * CT;
   PlainSrc<EXACT> src{psi + b * (int64_t)n * n, n};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_wave<MT, CT>(src, nb, fa, c2t0, Yre, Yim);
-  const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
+  fwd_engine<PR, MT, CT>(src, nb, fa, c2t0, Yre, Yim);
+  const int lane = lane_id();
   float2* out = y + b * (int64_t)m * m;
 #pragma unroll
   for (int c1t = 0; c1t < MT; ++c1t)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int c2 = (c2t0 + ct) * 16 + r16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int c1 = c1t * 16 + 4 * g + i;
-        if (c1 < m && c2 < m) out[(size_t)c1 * m + c2] = make_float2(Yre[c1t][ct][i], Yim[c1t][ct][i]);
+        const int2 rc = tile_rc<Orient<PR>::TR>(c1t, c2t0 + ct, i, lane);
+        if (rc.x < m && rc.y < m) out[(size_t)rc.x * m + rc.y] = make_float2(Yre[c1t][ct][i], Yim[c1t][ct][i]);
       }
     }
 }
@@ -50,49 +49,52 @@ struct CoefSrc {
 struct StoreSink {
   float2* __restrict__ out;
   int n;
-  __device__ __forceinline__ void operator()(int k1t, int k2t, const f32x4& re, const f32x4& im) const {
-    const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
-    const int k2 = k2t * 16 + r16;
+  template <bool TR>
+  __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& re, const f32x4& im) const {
+    const int lane = lane_id();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int k1 = k1t * 16 + 4 * g + i;
-      if (k1 < n && k2 < n) out[(size_t)k1 * n + k2] = make_float2(re[i], im[i]);
+      const int2 rc = tile_rc<TR>(k1t, k2t, i, lane);
+      if (rc.x < n && rc.y < n) out[(size_t)rc.x * n + rc.y] = make_float2(re[i], im[i]);
     }
   }
 };
 
 // Adjoint: one workgroup of W waves per patch; wave w takes column tiles
 // w, w + W, ...
-template <int MT>
+template <class PR, int MT>
 __global__ __launch_bounds__(256) void k_adjoint(const float2* __restrict__ y, float2* __restrict__ psi,
-                                                 int n, int m, int nb, const float4* __restrict__ ft) {
+                                                 int n, int m, int nb, const void* __restrict__ ft) {
   const int64_t b = blockIdx.x;
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   CoefSrc src{y + b * (int64_t)m * m, m};
   StoreSink sink{psi + b * (int64_t)n * n, n};
-  for (int kt2 = w; kt2 < nb; kt2 += nw) adj_wave_tile<MT>(src, nb, ft, kt2, sink);
+  for (int kt2 = w; kt2 < nb; kt2 += nw) adj_engine<PR, MT>(src, nb, ft, kt2, sink);
 }
 
-template <int MT, int CT>
+template <class PR, int MT, int CT>
 static hipError_t fwd_mt_ct(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
   constexpr int W = (MT + CT - 1) / CT;
   const bool exact = (p->n % 16 == 0) && ((uintptr_t)psi % 16 == 0);
   dim3 grid((unsigned)batch), block(64 * W);
   if (exact)
-    hipLaunchKernelGGL((k_forward<MT, CT, true>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
+    hipLaunchKernelGGL((k_forward<PR, MT, CT, true>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
   else
-    hipLaunchKernelGGL((k_forward<MT, CT, false>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
+    hipLaunchKernelGGL((k_forward<PR, MT, CT, false>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
   return hipGetLastError();
 }
 
 template <int MT>
 static hipError_t fwd_mt(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
-  // column tiles per wave: 4 only while the Y accumulators stay <= 128 registers
+  if (p->prec == PFTPIE_SPLIT_BF16) return fwd_mt_ct<PrecBF16, MT, (MT < 2 ? MT : 2)>(p, psi, y, batch, st);
+  if (p->prec == PFTPIE_SPLIT_FP16) return fwd_mt_ct<PrecF16, MT, (MT < 2 ? MT : 2)>(p, psi, y, batch, st);
+  // FP32: column tiles per wave from the plan (4 only while the Y
+  // accumulators stay within 128 registers)
   switch (p->fwd_ct) {
-    case 1: return fwd_mt_ct<MT, 1>(p, psi, y, batch, st);
-    case 2: if constexpr (MT >= 2) return fwd_mt_ct<MT, 2>(p, psi, y, batch, st); break;
-    case 4: if constexpr (MT >= 4 && MT <= 4) return fwd_mt_ct<MT, 4>(p, psi, y, batch, st); break;
-    case 3: if constexpr (MT == 3) return fwd_mt_ct<MT, 3>(p, psi, y, batch, st); break;
+    case 1: return fwd_mt_ct<PrecF32, MT, 1>(p, psi, y, batch, st);
+    case 2: if constexpr (MT >= 2) return fwd_mt_ct<PrecF32, MT, 2>(p, psi, y, batch, st); break;
+    case 4: if constexpr (MT == 4) return fwd_mt_ct<PrecF32, MT, 4>(p, psi, y, batch, st); break;
+    case 3: if constexpr (MT == 3) return fwd_mt_ct<PrecF32, MT, 3>(p, psi, y, batch, st); break;
   }
   return hipErrorInvalidValue;
 }
@@ -115,7 +117,12 @@ hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, 
 template <int MT>
 static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch, hipStream_t st) {
   dim3 grid((unsigned)batch), block(64 * adj_waves(p->nb));
-  hipLaunchKernelGGL((k_adjoint<MT>), grid, block, 0, st, y, psi, p->n, p->m, p->nb, p->ft);
+  if (p->prec == PFTPIE_SPLIT_BF16)
+    hipLaunchKernelGGL((k_adjoint<PrecBF16, MT>), grid, block, 0, st, y, psi, p->n, p->m, p->nb, p->ft);
+  else if (p->prec == PFTPIE_SPLIT_FP16)
+    hipLaunchKernelGGL((k_adjoint<PrecF16, MT>), grid, block, 0, st, y, psi, p->n, p->m, p->nb, p->ft);
+  else
+    hipLaunchKernelGGL((k_adjoint<PrecF32, MT>), grid, block, 0, st, y, psi, p->n, p->m, p->nb, p->ft);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@
 // Per sweep: k_pie_begin (copy O, clear accumulators / stats) and
 // k_pie_stats (||dO||^2, ||O||^2, non-finite count, Phi).
 #include "internal.hpp"
-#include "pft_engine.hpp"
+#include "pft_split.hpp"
 #include "pie.hpp"
 
 namespace pftpie {
@@ -30,7 +30,7 @@ __device__ __forceinline__ int pos_index(const int32_t* __restrict__ order, int 
   return ok ? j : 0;
 }
 
-template <int MT, int CT, bool EXACT>
+template <class PR, int MT, int CT, bool EXACT>
 __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieArgs a, int c0) {
   const int q = blockIdx.x;
   bool valid;
@@ -40,8 +40,8 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieAr
   const int2 ps = a.pos[j];
   GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_wave<MT, CT>(src, a.nb, a.fa, c2t0, Yre, Yim);
-  const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
+  fwd_engine<PR, MT, CT>(src, a.nb, a.fa, c2t0, Yre, Yim);
+  const int lane = lane_id();
   const int m = a.m;
   const float* amp = a.amp + (size_t)j * m * m;
   float2* res = a.R + (size_t)q * m * m;
@@ -50,10 +50,10 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieAr
   for (int c1t = 0; c1t < MT; ++c1t)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int c2 = (c2t0 + ct) * 16 + r16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int c1 = c1t * 16 + 4 * g + i;
+        const int2 rc = tile_rc<Orient<PR>::TR>(c1t, c2t0 + ct, i, lane);
+        const int c1 = rc.x, c2 = rc.y;
         if (c1 < m && c2 < m) {
           const float ur = Yre[c1t][ct][i], ui = Yim[c1t][ct][i];
           const float av = amp[(size_t)c1 * m + c2];
@@ -88,12 +88,13 @@ struct ScatterSink {
   double* __restrict__ E;
   int n, W, r, c, mode, norm, probe_step;
   float inv, beta;
-  __device__ __forceinline__ void operator()(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
-    const int lane = lane_id(), r16 = lane & 15, g = lane >> 4;
-    const int k2 = k2t * 16 + r16;
+  template <bool TR>
+  __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
+    const int lane = lane_id();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int k1 = k1t * 16 + 4 * g + i;
+      const int2 rc = tile_rc<TR>(k1t, k2t, i, lane);
+      const int k1 = rc.x, k2 = rc.y;
       if (k1 < n && k2 < n) {
         const float2 d = make_float2(xre[i] * inv, xim[i] * inv);
         const float2 p = P[(size_t)k1 * n + k2];
@@ -120,7 +121,7 @@ struct ScatterSink {
   }
 };
 
-template <int MT>
+template <class PR, int MT>
 __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
   const int q = blockIdx.x;
   const int j = pos_index(a.order, a.J, c0, q, nullptr);
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
   } src{a.R + (size_t)q * a.m * a.m, a.m};
   ScatterSink sink{a.O, a.P, a.numO, a.D, a.numP, a.E, a.n, a.W, ps.x, ps.y,
                    a.mode, a.norm, a.probe_step, a.inv_n2, a.beta};
-  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_wave_tile<MT>(src, a.nb, a.ft, kt2, sink);
+  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, a.ft, kt2, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,23 +307,33 @@ __global__ __launch_bounds__(256) void k_crop_amp(const float* __restrict__ I, i
 // ---------------------------------------------------------------------------
 // launch
 
-template <int MT, int CT>
+template <class PR, int MT, int CT>
 static void fwd_launch(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   constexpr int W = (MT + CT - 1) / CT;
   dim3 grid(cnt), block(64 * W);
   if (a.n % 16 == 0)
-    hipLaunchKernelGGL((k_pie_forward<MT, CT, true>), grid, block, 0, st, a, c0);
+    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, true>), grid, block, 0, st, a, c0);
   else
-    hipLaunchKernelGGL((k_pie_forward<MT, CT, false>), grid, block, 0, st, a, c0);
+    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, false>), grid, block, 0, st, a, c0);
+}
+
+template <class PR, int MT>
+static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
+  // forward: at most 4 waves per patch so phi_part has a slot per wave
+  constexpr int CT = (MT <= 2) ? MT : 2;
+  fwd_launch<PR, MT, CT>(a, c0, cnt, st);
+  dim3 grid(cnt), block(64 * adj_waves(a.nb));
+  hipLaunchKernelGGL((k_pie_adjoint<PR, MT>), grid, block, 0, st, a, c0);
 }
 
 template <int MT>
 static void chunk_mt(const PieArgs& a, int c0, int cnt, hipStream_t st) {
-  // forward: at most 4 waves per patch so phi_part has a slot per wave
-  constexpr int CT = (MT <= 2) ? MT : 2;
-  fwd_launch<MT, CT>(a, c0, cnt, st);
-  dim3 grid(cnt), block(64 * adj_waves(a.nb));
-  hipLaunchKernelGGL((k_pie_adjoint<MT>), grid, block, 0, st, a, c0);
+  if (a.prec == PFTPIE_SPLIT_BF16)
+    chunk_prec<PrecBF16, MT>(a, c0, cnt, st);
+  else if (a.prec == PFTPIE_SPLIT_FP16)
+    chunk_prec<PrecF16, MT>(a, c0, cnt, st);
+  else
+    chunk_prec<PrecF32, MT>(a, c0, cnt, st);
 }
 
 static int ew_blocks(size_t work) {

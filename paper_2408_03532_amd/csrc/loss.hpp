@@ -8,8 +8,9 @@ namespace pftpie {
 struct LossArgs {
   int n, m, nb, mt, J, H, W;
   const int2* pos;
-  const float4* fa;
-  const float4* ft;
+  const void* fa;
+  const void* ft;
+  int prec;
   const float2* O;
   const float2* P;
   const float* amp;

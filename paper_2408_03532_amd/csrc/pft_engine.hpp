@@ -135,7 +135,7 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* _
 
 // Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
 // returns Y[row][col0..col0+3] (zeros outside m x m).  FT holds NB x MT
-// blocks.  sink(k1t, kt2, Xre, Xim) receives each finished tile.
+// blocks.  sink.put<false>(k1t, kt2, Xre, Xim) receives each finished tile.
 template <int MT, class YSrc, class Sink>
 __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const float4* __restrict__ FT,
                                               int kt2, Sink& sink) {
@@ -222,8 +222,8 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const fl
       }
     }
     if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fa[0], fb[0]);
-    sink(k1t, kt2, Xre0, Xim0);
-    if (two) sink(k1t + 1, kt2, Xre1, Xim1);
+    sink.template put<false>(k1t, kt2, Xre0, Xim0);
+    if (two) sink.template put<false>(k1t + 1, kt2, Xre1, Xim1);
   }
 }
 

@@ -21,8 +21,9 @@ struct PieArgs {
   int bb_r0, bb_c0, bb_h, bb_w;  // bounding box of all windows
   const int2* pos;               // [J] (row, col)
   const int32_t* order;          // [J] or null
-  const float4* fa;
-  const float4* ft;
+  const void* fa;
+  const void* ft;
+  int prec;
   float inv_n2;
   // parameters
   int mode, norm, probe_step;

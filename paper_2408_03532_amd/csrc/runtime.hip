@@ -44,8 +44,6 @@ static pftpie_status check_batch_io(const pftpie_plan_s* p, const void* in, size
     return fail(PFTPIE_E_INVALID, std::string(what) + ": data pointers must be 8-byte aligned");
   if (overlaps(in, in_elems * batch * 8, out, out_elems * batch * 8))
     return fail(PFTPIE_E_INVALID, std::string(what) + ": input and output overlap");
-  if (p->prec != PFTPIE_FP32)
-    return fail(PFTPIE_E_UNSUPPORTED, std::string(what) + ": precision not available for this call");
   return PFTPIE_OK;
 }
 
@@ -95,9 +93,22 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
     return hip_fail(e, "plan_create: hipGetDevice");
   }
   std::vector<float> fa, ft;
-  build_twiddle_tables(n, m, p->fa_ctiles, fa, ft);
-  p->fa_bytes = fa.size() * sizeof(float);
-  p->ft_bytes = ft.size() * sizeof(float);
+  std::vector<uint16_t> fa16, ft16;
+  const void* fa_src;
+  const void* ft_src;
+  if (prec == PFTPIE_FP32) {
+    build_twiddle_tables(n, m, p->fa_ctiles, fa, ft);
+    p->fa_bytes = fa.size() * sizeof(float);
+    p->ft_bytes = ft.size() * sizeof(float);
+    fa_src = fa.data();
+    ft_src = ft.data();
+  } else {
+    build_split_tables(n, m, p->fa_ctiles, prec == PFTPIE_SPLIT_BF16 ? 1 : 2, fa16, ft16);
+    p->fa_bytes = fa16.size() * sizeof(uint16_t);
+    p->ft_bytes = ft16.size() * sizeof(uint16_t);
+    fa_src = fa16.data();
+    ft_src = ft16.data();
+  }
   e = hipMalloc((void**)&p->fa, p->fa_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&p->ft, p->ft_bytes);
   if (e != hipSuccess) {
@@ -105,8 +116,8 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
     delete p;
     return fail(PFTPIE_E_NOMEM, std::string("plan_create: hipMalloc: ") + hipGetErrorString(e));
   }
-  e = hipMemcpy(p->fa, fa.data(), p->fa_bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->ft, ft.data(), p->ft_bytes, hipMemcpyHostToDevice);
+  e = hipMemcpy(p->fa, fa_src, p->fa_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->ft, ft_src, p->ft_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(p->fa);
     (void)hipFree(p->ft);

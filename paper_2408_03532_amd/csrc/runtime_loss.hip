@@ -31,7 +31,6 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 pftpie_status check_common(const pie_scan_s* s, const void* O, const void* P, const float* amp, void* ws,
                            size_t ws_bytes, const char* who) {
   if (!s) return fail(PFTPIE_E_INVALID, std::string(who) + ": scan is NULL");
-  if (s->plan->prec != PFTPIE_FP32) return fail(PFTPIE_E_UNSUPPORTED, std::string(who) + ": plan precision");
   if (!O || !P || !amp) return fail(PFTPIE_E_INVALID, std::string(who) + ": NULL object, probe or amplitudes");
   if ((uintptr_t)O % 8 || (uintptr_t)P % 8 || (uintptr_t)amp % 4)
     return fail(PFTPIE_E_INVALID, std::string(who) + ": misaligned object, probe or amplitudes");
@@ -57,6 +56,7 @@ LossArgs base_args(const pie_scan_s* s, const void* O, const void* P, const floa
   a.pos = s->pos;
   a.fa = pl->fa;
   a.ft = pl->ft;
+  a.prec = pl->prec;
   a.O = static_cast<const float2*>(O);
   a.P = static_cast<const float2*>(P);
   a.amp = amp;

@@ -49,7 +49,6 @@ pftpie_status check_params(const pie_scan_s* s, const pie_params* p) {
   if (!std::isfinite(p->beta) || !std::isfinite(p->gamma) || !std::isfinite(p->alpha))
     return fail(PFTPIE_E_INVALID, "pie: non-finite step or regulariser");
   if (p->gamma < 0.f || p->alpha < 0.f) return fail(PFTPIE_E_INVALID, "pie: gamma and alpha must be >= 0");
-  if (s->plan->prec != PFTPIE_FP32) return fail(PFTPIE_E_UNSUPPORTED, "pie: plan precision not available");
   return PFTPIE_OK;
 }
 
@@ -173,6 +172,7 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.order = order_dev;
   a.fa = pl->fa;
   a.ft = pl->ft;
+  a.prec = pl->prec;
   a.inv_n2 = (float)(1.0 / ((double)pl->n * pl->n));
   a.mode = mode;
   a.norm = p->norm;

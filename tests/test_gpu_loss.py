@@ -92,3 +92,16 @@ def test_loss_gradient_at_truth_is_small(pk):
     L = pk.amp_loss(O, P, scan, A).item()
     scale = float(np.sum(case["amp"].astype(np.float64) ** 2))
     assert L <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-3), ("split_fp16", 1e-4)])
+def test_split_precision_loss_and_gradient(pk, precision, tol):
+    case = workloads.amp_loss_case(**SMALL)
+    O, P, A = to_dev(case)
+    scan = pk.Scan(case["pos"], O.shape, 64, 16, precision=precision)
+    L = pk.amp_loss(O, P, scan, A)
+    gO, gP = pk.amp_loss_grad(O, P, scan, A)
+    Lr, gOr, gPr = oloss.amp_loss_grad(case["obj"], case["probe"], case["pos"], case["amp"], 16)
+    assert abs(L.item() - Lr) <= tol * Lr
+    assert rel(gO.cpu().numpy(), gOr) <= tol
+    assert rel(gP.cpu().numpy(), gPr) <= tol

@@ -20,6 +20,12 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 TOL_PATCH = 3e-5
+# split hi+lo operands: products hi*hi + hi*lo + lo*hi leave the lo*lo term
+# and the 16-bit rounding of the lo parts, ~2^-16 (bf16, 8-bit significand)
+# or ~2^-22 (fp16, 11-bit) relative per operand, times the growth over the
+# two stages: bf16 lands near 5e-6, fp16 near 1e-7.
+TOLS = {"fp32": (1e-5, 3e-5), "split_bf16": (1e-4, 3e-4), "split_fp16": (1e-5, 3e-5)}
+PRECS = sorted(TOLS)
 
 
 def rel(a, b):
@@ -44,30 +50,34 @@ SHAPES = [(32, 16, 5), (64, 16, 3), (40, 24, 4), (17, 5, 3), (128, 32, 4), (256,
           (96, 80, 2)]
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,m,batch", SHAPES)
-def test_forward_matches_oracle(pkg, n, m, batch):
-    print(f"forward n={n} m={m} batch={batch}", flush=True)
+def test_forward_matches_oracle(pkg, n, m, batch, prec):
+    print(f"forward n={n} m={m} batch={batch} {prec}", flush=True)
     x = workloads.pft_patches(n, range(batch), seed=100 + n)
-    y = pkg.pft2d_forward(torch.from_numpy(x).cuda(), m)
+    y = pkg.pft2d_forward(torch.from_numpy(x).cuda(), m, prec)
     torch.cuda.synchronize()
     ref = opft.forward(x, m)
     got = y.cpu().numpy()
     assert got.shape == (batch, m, m)
-    assert rel(got, ref) <= TOL
-    assert per_patch_rel(got, ref).max() <= TOL_PATCH
+    tol, tol_patch = TOLS[prec]
+    assert rel(got, ref) <= tol
+    assert per_patch_rel(got, ref).max() <= tol_patch
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,m,batch", SHAPES)
-def test_adjoint_matches_oracle(pkg, n, m, batch):
-    print(f"adjoint n={n} m={m} batch={batch}", flush=True)
+def test_adjoint_matches_oracle(pkg, n, m, batch, prec):
+    print(f"adjoint n={n} m={m} batch={batch} {prec}", flush=True)
     y = workloads.pft_coeffs(m, range(batch), seed=200 + n)
-    x = pkg.pft2d_adjoint(torch.from_numpy(y).cuda(), n)
+    x = pkg.pft2d_adjoint(torch.from_numpy(y).cuda(), n, prec)
     torch.cuda.synchronize()
     ref = opft.adjoint(y, n)
     got = x.cpu().numpy()
     assert got.shape == (batch, n, n)
-    assert rel(got, ref) <= TOL
-    assert per_patch_rel(got, ref).max() <= TOL_PATCH
+    tol, tol_patch = TOLS[prec]
+    assert rel(got, ref) <= tol
+    assert per_patch_rel(got, ref).max() <= tol_patch
 
 
 def test_unaligned_input_takes_the_masked_path(pkg):
@@ -119,18 +129,20 @@ def test_autograd_backward_is_the_adjoint(pkg):
     assert rel(x.grad.cpu().numpy(), ref) <= TOL
 
 
-def test_standalone_batch_full_size_sampled(pkg):
+@pytest.mark.parametrize("prec", PRECS)
+def test_standalone_batch_full_size_sampled(pkg, prec):
     """The 4096 x 256^2, m = 64 batch in the benchmark's launch
     configuration; 24 sampled patches checked against the oracle."""
     n, m, B = 256, 64, 4096
+    TOL = TOLS[prec][0]
     idx = np.random.default_rng(0).choice(B, 24, replace=False)
     x = torch.empty(B, n, n, dtype=torch.complex64, device="cuda")
     for b0 in range(0, B, 512):
         x[b0:b0 + 512] = torch.from_numpy(workloads.pft_patches(n, range(b0, b0 + 512))).cuda()
-    y = pkg.pft2d_forward(x, m)
+    y = pkg.pft2d_forward(x, m, prec)
     yin = torch.empty(B, m, m, dtype=torch.complex64, device="cuda")
     yin.copy_(torch.from_numpy(workloads.pft_coeffs(m, range(B))).cuda())
-    xa = pkg.pft2d_adjoint(yin, n)
+    xa = pkg.pft2d_adjoint(yin, n, prec)
     torch.cuda.synchronize()
     xs = workloads.pft_patches(n, idx)
     assert rel(y[idx].cpu().numpy(), opft.forward(xs, m)) <= TOL

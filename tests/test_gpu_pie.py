@@ -37,9 +37,9 @@ def tiny():
     return workloads.tiny_pie()
 
 
-def run_gpu(pk, case, obj0, probe0, amp, m, params, order=None, sweeps=1):
+def run_gpu(pk, case, obj0, probe0, amp, m, params, order=None, sweeps=1, precision="fp32"):
     n = case["probe"].shape[0]
-    scan = pk.Scan(case["pos"], obj0.shape, n, m)
+    scan = pk.Scan(case["pos"], obj0.shape, n, m, precision=precision)
     O = torch.from_numpy(obj0.astype(np.complex64)).cuda()
     P = torch.from_numpy(probe0.astype(np.complex64)).cuda()
     A = torch.from_numpy(amp.astype(np.float32)).cuda()
@@ -166,3 +166,18 @@ def test_invalid_arguments_are_rejected(pk, tiny):
         pk.pie_sweep(O, P, scan, A, pk.PieParams(batch=0))
     with pytest.raises(pk.PftpieError, match="overlap"):
         pk.pie_sweep(O, O.view(-1)[: 32 * 32].view(32, 32), scan, A, pk.PieParams())
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-4), ("split_fp16", 1e-5)])
+def test_split_precision_sweeps(pk, tiny, precision, tol):
+    """One sweep in each split precision against the FP64 oracle."""
+    m = tiny["m"]
+    for mode in (dict(batch=1, norm=0, beta=1.0), dict(batch=64, norm=1, beta=1.0, alpha=1e-3),
+                 dict(batch=8, norm=1, beta=0.8, gamma=0.5, alpha=1e-3)):
+        P0 = tiny["probe"] * (1.0 + 0.05j) if mode.get("gamma", 0) else tiny["probe"]
+        O, P, st = run_gpu(pk, tiny, tiny["init"], P0, tiny["amp"], m, pk.PieParams(**mode),
+                           precision=precision)
+        Or, Pr, sr = opie.pie_sweep(tiny["init"], P0, tiny["pos"], tiny["amp"], m, **mode)
+        assert rel(O, Or) <= tol
+        assert rel(P, Pr) <= tol
+        assert abs(st[0][0] - sr[0]) <= tol * sr[0]
