@@ -129,3 +129,50 @@ __device__ __forceinline__ f32x4 mfma3(const typename PR::V& ah, const typename 
 }
 
 }  // namespace pftpie
+
+namespace pftpie {
+
+// ---------------------------------------------------------------------------
+// Twiddle-table accessors.  A table is an array of 2048-byte blocks (FP32:
+// 128 float4 in two 1 KB planes; split: hi plane then lo plane).  TabG reads
+// from global memory (L2-resident), TabL from a copy in LDS.
+
+typedef const __attribute__((address_space(3))) char* lds_cptr;
+
+struct TabG {
+  const char* __restrict__ p;
+  __device__ __forceinline__ c4 f32(size_t blk, int lane) const {
+    return load_tw(reinterpret_cast<const float4*>(p + blk * 2048), lane);
+  }
+  template <class PR>
+  __device__ __forceinline__ TwS<PR> s16(size_t blk, int lane) const {
+    return load_tws<PR>(p + blk * 2048, lane);
+  }
+};
+
+struct TabL {
+  lds_cptr p;
+  __device__ __forceinline__ c4 f32(size_t blk, int lane) const {
+    typedef const __attribute__((address_space(3))) f32x4* q_t;
+    const q_t q = reinterpret_cast<q_t>(p + blk * 2048);
+    const f32x4 a = q[lane], b = q[64 + lane];
+    c4 r;
+    r.v[0] = make_float2(a.x, a.y);
+    r.v[1] = make_float2(a.z, a.w);
+    r.v[2] = make_float2(b.x, b.y);
+    r.v[3] = make_float2(b.z, b.w);
+    return r;
+  }
+  template <class PR>
+  __device__ __forceinline__ TwS<PR> s16(size_t blk, int lane) const {
+    typedef const __attribute__((address_space(3))) typename PR::V* q_t;
+    const q_t q = reinterpret_cast<q_t>(p + blk * 2048);
+    TwS<PR> r;
+    r.h = q[lane];
+    r.l = q[64 + lane];
+    return r;
+  }
+};
+
+}  // namespace pftpie
+

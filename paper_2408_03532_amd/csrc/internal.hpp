@@ -14,6 +14,7 @@ namespace pftpie {
 
 constexpr int kMaxN = 4096;
 constexpr int kMaxM = 128;  // 8 accumulator tiles per axis
+constexpr size_t kMaxLdsTable = 160 * 1024;  // LDS per compute unit on gfx950
 
 // Forward work split for MT = ceil(m/16) output tiles per axis: each wave
 // owns CT column tiles, W = ceil(MT / CT) waves per patch.  Valid CT: 1, 2
@@ -35,6 +36,8 @@ struct pftpie_plan_s {
   int nb, mt;        // ceil(n/16), ceil(m/16)
   int fa_ctiles;     // column tiles allocated in FA (covers every forward split)
   int fwd_ct;        // forward column tiles per wave
+  int use_lds;       // persistent LDS-table kernels for the plain transforms
+  int num_cu;        // compute units of the plan's device
   int device;
   void* fa;          // device FA table (float4 blocks, or split 16-bit blocks)
   void* ft;          // device FT table

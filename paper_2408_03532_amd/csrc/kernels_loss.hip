@@ -23,7 +23,7 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(Loss
   const int2 ps = a.pos[j];
   GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, a.nb, a.fa, c2t0, Yre, Yim);
+  fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim);
   const int lane = lane_id();
   const int m = a.m;
   const float* amp = a.amp + (size_t)j * m * m;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_loss_adjoint(LossArgs a) {
   GradSrc src{a.Uc + (size_t)j * mm, a.amp + (size_t)j * mm, a.m};
   const float scale = a.scale_dev ? (float)a.scale_dev[0] : 1.f;
   GradSink sink{a.O, a.P, a.gO, a.gP, a.n, a.W, ps.x, ps.y, scale};
-  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, a.ft, kt2, sink);
+  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, TabG{static_cast<const char*>(a.ft)}, kt2, sink);
 }
 
 __global__ __launch_bounds__(256) void k_loss_reduce(LossArgs a) {

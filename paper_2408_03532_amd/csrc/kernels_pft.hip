@@ -16,7 +16,7 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_forward(
   const int c2t0 = w * CT;
   PlainSrc<EXACT> src{psi + b * (int64_t)n * n, n};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, nb, fa, c2t0, Yre, Yim);
+  fwd_engine<PR, MT, CT>(src, nb, TabG{static_cast<const char*>(fa)}, c2t0, Yre, Yim);
   const int lane = lane_id();
   float2* out = y + b * (int64_t)m * m;
 #pragma unroll
@@ -69,13 +69,89 @@ __global__ __launch_bounds__(256) void k_adjoint(const float2* __restrict__ y, f
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   CoefSrc src{y + b * (int64_t)m * m, m};
   StoreSink sink{psi + b * (int64_t)n * n, n};
-  for (int kt2 = w; kt2 < nb; kt2 += nw) adj_engine<PR, MT>(src, nb, ft, kt2, sink);
+  for (int kt2 = w; kt2 < nb; kt2 += nw) adj_engine<PR, MT>(src, nb, TabG{static_cast<const char*>(ft)}, kt2, sink);
+}
+
+// Persistent variants: one workgroup per compute unit copies the whole
+// twiddle table into LDS once, then its waves pull work items (patch,
+// column-tile group) / (patch, column tile) until the batch is done.
+constexpr int kLdsThreads = 512;
+
+__device__ __forceinline__ void copy_table_to_lds(f32x4* smem, const f32x4* __restrict__ tab, int n16) {
+  for (int i = threadIdx.x; i < n16; i += blockDim.x) smem[i] = tab[i];
+  __syncthreads();
+}
+
+template <class PR, int MT, int CT>
+__global__ __launch_bounds__(kLdsThreads) void k_forward_lds(const float2* __restrict__ psi, float2* __restrict__ y,
+                                                             int n, int m, int nb, const f32x4* __restrict__ tab,
+                                                             int tab16, int64_t batch) {
+  extern __shared__ f32x4 smem[];
+  copy_table_to_lds(smem, tab, tab16);
+  const TabL T{(lds_cptr)smem};
+  constexpr int W = (MT + CT - 1) / CT;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int64_t items = batch * W;
+  const int lane = lane_id();
+  for (int64_t it = (int64_t)blockIdx.x * nwaves + wave; it < items; it += (int64_t)gridDim.x * nwaves) {
+    const int64_t b = it / W;
+    const int c2t0 = (int)(it % W) * CT;
+    PlainSrc<true> src{psi + b * (int64_t)n * n, n};
+    f32x4 Yre[MT][CT], Yim[MT][CT];
+    fwd_engine<PR, MT, CT>(src, nb, T, c2t0, Yre, Yim);
+    float2* out = y + b * (int64_t)m * m;
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int2 rc = tile_rc<Orient<PR>::TR>(c1t, c2t0 + ct, i, lane);
+          if (rc.x < m && rc.y < m) out[(size_t)rc.x * m + rc.y] = make_float2(Yre[c1t][ct][i], Yim[c1t][ct][i]);
+        }
+  }
+}
+
+template <class PR, int MT>
+__global__ __launch_bounds__(kLdsThreads) void k_adjoint_lds(const float2* __restrict__ y, float2* __restrict__ psi,
+                                                             int n, int m, int nb, const f32x4* __restrict__ tab,
+                                                             int tab16, int64_t batch) {
+  extern __shared__ f32x4 smem[];
+  copy_table_to_lds(smem, tab, tab16);
+  const TabL T{(lds_cptr)smem};
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int64_t items = batch * nb;
+  for (int64_t it = (int64_t)blockIdx.x * nwaves + wave; it < items; it += (int64_t)gridDim.x * nwaves) {
+    const int64_t b = it / nb;
+    const int kt2 = (int)(it % nb);
+    CoefSrc src{y + b * (int64_t)m * m, m};
+    StoreSink sink{psi + b * (int64_t)n * n, n};
+    adj_engine<PR, MT>(src, nb, T, kt2, sink);
+  }
+}
+
+template <class K>
+static hipError_t launch_lds(K kernel, const pftpie_plan_s* p, size_t tab_bytes, int64_t items, hipStream_t st,
+                             const float2* in, float2* out, const void* tab, int64_t batch) {
+  // every instantiation is allowed the table's dynamic LDS once
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)tab_bytes);
+  if (e != hipSuccess) return e;
+  const int64_t waves = kLdsThreads / 64;
+  int64_t grid = (items + waves - 1) / waves;
+  if (grid > p->num_cu) grid = p->num_cu;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kLdsThreads), tab_bytes, st, in, out, p->n, p->m, p->nb,
+                     static_cast<const f32x4*>(tab), (int)(tab_bytes / 16), batch);
+  return hipGetLastError();
 }
 
 template <class PR, int MT, int CT>
 static hipError_t fwd_mt_ct(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
   constexpr int W = (MT + CT - 1) / CT;
   const bool exact = (p->n % 16 == 0) && ((uintptr_t)psi % 16 == 0);
+  // (CT = 4 needs more than the 256 registers a 512-thread workgroup leaves)
+  if (exact && p->use_lds && CT <= 2 && p->fa_bytes <= kMaxLdsTable)
+    return launch_lds(k_forward_lds<PR, MT, CT>, p, p->fa_bytes, batch * W, st, psi, y, p->fa, batch);
   dim3 grid((unsigned)batch), block(64 * W);
   if (exact)
     hipLaunchKernelGGL((k_forward<PR, MT, CT, true>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
@@ -116,6 +192,14 @@ hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, 
 
 template <int MT>
 static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch, hipStream_t st) {
+  if (p->use_lds && p->ft_bytes <= kMaxLdsTable) {
+    const int64_t items = batch * p->nb;
+    if (p->prec == PFTPIE_SPLIT_BF16)
+      return launch_lds(k_adjoint_lds<PrecBF16, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+    if (p->prec == PFTPIE_SPLIT_FP16)
+      return launch_lds(k_adjoint_lds<PrecF16, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+    return launch_lds(k_adjoint_lds<PrecF32, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+  }
   dim3 grid((unsigned)batch), block(64 * adj_waves(p->nb));
   if (p->prec == PFTPIE_SPLIT_BF16)
     hipLaunchKernelGGL((k_adjoint<PrecBF16, MT>), grid, block, 0, st, y, psi, p->n, p->m, p->nb, p->ft);

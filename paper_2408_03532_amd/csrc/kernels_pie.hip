@@ -40,7 +40,7 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieAr
   const int2 ps = a.pos[j];
   GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, a.nb, a.fa, c2t0, Yre, Yim);
+  fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim);
   const int lane = lane_id();
   const int m = a.m;
   const float* amp = a.amp + (size_t)j * m * m;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
   } src{a.R + (size_t)q * a.m * a.m, a.m};
   ScatterSink sink{a.O, a.P, a.numO, a.D, a.numP, a.E, a.n, a.W, ps.x, ps.y,
                    a.mode, a.norm, a.probe_step, a.inv_n2, a.beta};
-  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, a.ft, kt2, sink);
+  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, TabG{static_cast<const char*>(a.ft)}, kt2, sink);
 }
 
 // ---------------------------------------------------------------------------

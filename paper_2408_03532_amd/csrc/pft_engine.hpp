@@ -56,9 +56,9 @@ struct PlainSrc {
 
 // Forward engine.  NB = ceil(n/16) row strips / column blocks.  FA holds
 // ctiles x NB blocks.  c2t0: first column tile this wave owns.
-template <int MT, int CT, class Src>
-__device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* __restrict__ FA,
-                                         int c2t0, f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT]) {
+template <int MT, int CT, class Src, class Tab>
+__device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
+                                         f32x4 (&Yim)[MT][CT]) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -97,7 +97,7 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* _
     auto fetch = [&](int kb, c4& a, c4(&f)[CT]) {
       a = src.load(row, kb * 16 + 4 * g);
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) f[ct] = load_tw(FA + ((size_t)(c2t0 + ct) * NB + kb) * 128, lane);
+      for (int ct = 0; ct < CT; ++ct) f[ct] = FA.f32((size_t)(c2t0 + ct) * NB + kb, lane);
     };
     c4 a0, a1, f0[CT], f1[CT];
     fetch(0, a0, f0);
@@ -114,7 +114,7 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* _
     // stage 2: Y[c1 tile][own tiles] += F[c1 tile, strip] * T[strip, own tiles]
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
-      c4 fb = load_tw(FA + ((size_t)c1t * NB + strip) * 128, lane);
+      c4 fb = FA.f32((size_t)c1t * NB + strip, lane);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float fr = fb.v[i].x, fi = fb.v[i].y, nfi = -fi;
@@ -136,9 +136,8 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const float4* _
 // Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
 // returns Y[row][col0..col0+3] (zeros outside m x m).  FT holds NB x MT
 // blocks.  sink.put<false>(k1t, kt2, Xre, Xim) receives each finished tile.
-template <int MT, class YSrc, class Sink>
-__device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const float4* __restrict__ FT,
-                                              int kt2, Sink& sink) {
+template <int MT, class YSrc, class Sink, class Tab>
+__device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Tab& FT, int kt2, Sink& sink) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
   f32x4 Sre[MT], Sim[MT];
@@ -165,7 +164,7 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const fl
     }
   };
   auto fetch1 = [&](int kb, c4& f, c4(&y)[MT]) {
-    f = load_tw(FT + ((size_t)kt2 * MT + kb) * 128, lane);
+    f = FT.f32((size_t)kt2 * MT + kb, lane);
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
   };
@@ -191,8 +190,8 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const fl
   // step's products issue (ping-pong buffers, no register copies).
   auto fetch2 = [&](int k1t, int c1t, c4& fa, c4& fb) {
     const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
-    fa = load_tw(FT + ((size_t)k1t * MT + c1t) * 128, lane);
-    fb = load_tw(FT + ((size_t)k1b * MT + c1t) * 128, lane);
+    fa = FT.f32((size_t)k1t * MT + c1t, lane);
+    fb = FT.f32((size_t)k1b * MT + c1t, lane);
   };
   c4 fa[2], fb[2];
   fetch2(0, 0, fa[0], fb[0]);

@@ -79,13 +79,15 @@ __device__ __forceinline__ SplitOp<PR> make_op(const float (&re)[8], const float
   return o;
 }
 
-// Forward, split: Y^T tiles [MT][CT] for the wave's CT column tiles.
-template <class PR, int MT, int CT, class Src>
-__device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const void* __restrict__ FA, int c2t0,
+// Forward, split: Y^T tiles [MT][CT] for the wave's CT column tiles.  The
+// patch chunks are fetched three blocks ahead (a 16x16x32 MFMA block is only
+// ~200 cycles of work, far shorter than a memory round trip); twiddles one
+// block ahead.
+template <class PR, int MT, int CT, class Src, class Tab>
+__device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab& FA, int c2t0,
                                                f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT]) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
-  const char* fa = static_cast<const char*>(FA);
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
@@ -121,25 +123,29 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const voi
         Tim[ct] = PR::mfma(op.iml, f[ct].h, Tim[ct]);
       }
     };
-    auto fetch = [&](int kb, c4& a, TwS<PR>(&f)[CT]) {
-      a = src.load(row, kb * 16 + 4 * g);
+    auto load_a = [&](int kb) { return src.load(row, (kb < NB ? kb : NB - 1) * 16 + 4 * g); };
+    auto load_f = [&](int kb, TwS<PR>(&f)[CT]) {
+      const int k = kb < NB ? kb : NB - 1;
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        f[ct] = load_tws<PR>(fa + ((size_t)(c2t0 + ct) * NB + kb) * 2048, lane);
+      for (int ct = 0; ct < CT; ++ct) f[ct] = FA.template s16<PR>((size_t)(c2t0 + ct) * NB + k, lane);
     };
-    c4 a0, a1;
-    TwS<PR> f0[CT], f1[CT];
-    fetch(0, a0, f0);
-    int kb = 0;
-    for (; kb + 1 < NB; kb += 2) {
-      fetch(kb + 1, a1, f1);
-      __builtin_amdgcn_sched_barrier(0);
-      stage1(a0, f0);
-      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
-      __builtin_amdgcn_sched_barrier(0);
-      stage1(a1, f1);
+    c4 a[4];
+    TwS<PR> f[2][CT];
+    a[0] = load_a(0);
+    a[1] = load_a(1);
+    a[2] = load_a(2);
+    load_f(0, f[0]);
+    for (int kb = 0; kb < NB; kb += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (kb + u < NB) {
+          a[(u + 3) & 3] = load_a(kb + u + 3);
+          load_f(kb + u + 1, f[(u + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);
+          stage1(a[u], f[u & 1]);
+        }
+      }
     }
-    if (kb < NB) stage1(a0, f0);
     // stage 2 (transposed): Y^T[c2][c1] += sum_{k1 in strip} T[k1][c2] F[c1][k1]
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -154,7 +160,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const voi
       const SplitOp<PR> op = make_op<PR>(re, im);
 #pragma unroll
       for (int c1t = 0; c1t < MT; ++c1t) {
-        const TwS<PR> fb = load_tws<PR>(fa + ((size_t)c1t * NB + strip) * 2048, lane);
+        const TwS<PR> fb = FA.template s16<PR>((size_t)c1t * NB + strip, lane);
         Yre[c1t][ct] = PR::mfma(op.reh, fb.h, Yre[c1t][ct]);
         Yim[c1t][ct] = PR::mfma(op.imh, fb.h, Yim[c1t][ct]);
         Yre[c1t][ct] = PR::mfma(op.reh, fb.l, Yre[c1t][ct]);
@@ -167,12 +173,11 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const voi
 }
 
 // Adjoint, split, one column tile kt2: sink.put<true> receives X^T tiles.
-template <class PR, int MT, class YSrc, class Sink>
-__device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, const void* __restrict__ FT,
-                                                    int kt2, Sink& sink) {
+template <class PR, int MT, class YSrc, class Sink, class Tab>
+__device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, const Tab& FT, int kt2,
+                                                    Sink& sink) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
-  const char* ft = static_cast<const char*>(FT);
   f32x4 Sre[MT], Sim[MT];
 #pragma unroll
   for (int a = 0; a < MT; ++a) {
@@ -182,7 +187,7 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
   // stage 1: S[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2])
 #pragma unroll
   for (int kb = 0; kb < MT; ++kb) {
-    const TwS<PR> f = load_tws<PR>(ft + ((size_t)kt2 * MT + kb) * 2048, lane);
+    const TwS<PR> f = FT.template s16<PR>((size_t)kt2 * MT + kb, lane);
     c4 y[MT];
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
@@ -217,8 +222,8 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
   // two row tiles at a time, ping-pong twiddle fetches
   auto fetch2 = [&](int k1t, int c1t, TwS<PR>& fa, TwS<PR>& fb) {
     const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
-    fa = load_tws<PR>(ft + ((size_t)k1t * MT + c1t) * 2048, lane);
-    fb = load_tws<PR>(ft + ((size_t)k1b * MT + c1t) * 2048, lane);
+    fa = FT.template s16<PR>((size_t)k1t * MT + c1t, lane);
+    fb = FT.template s16<PR>((size_t)k1b * MT + c1t, lane);
   };
   TwS<PR> fa[2], fb[2];
   fetch2(0, 0, fa[0], fb[0]);
@@ -257,21 +262,26 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
 // ---------------------------------------------------------------------------
 // precision-generic entry points used by the kernels
 
-template <class PR, int MT, int CT, class Src>
-__device__ __forceinline__ void fwd_engine(const Src& src, int NB, const void* FA, int c2t0,
+template <class PR, int MT, int CT, class Src, class Tab>
+__device__ __forceinline__ void fwd_engine(const Src& src, int NB, const Tab& FA, int c2t0,
                                            f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT]) {
   if constexpr (Orient<PR>::TR)
     fwd_wave_split<PR, MT, CT>(src, NB, FA, c2t0, Yre, Yim);
   else
-    fwd_wave<MT, CT>(src, NB, static_cast<const float4*>(FA), c2t0, Yre, Yim);
+    fwd_wave<MT, CT>(src, NB, FA, c2t0, Yre, Yim);
 }
 
-template <class PR, int MT, class YSrc, class Sink>
-__device__ __forceinline__ void adj_engine(const YSrc& ysrc, int NB, const void* FT, int kt2, Sink& sink) {
+template <class PR, int MT, class YSrc, class Sink, class Tab>
+__device__ __forceinline__ void adj_engine(const YSrc& ysrc, int NB, const Tab& FT, int kt2, Sink& sink) {
   if constexpr (Orient<PR>::TR)
     adj_wave_tile_split<PR, MT>(ysrc, NB, FT, kt2, sink);
   else
-    adj_wave_tile<MT>(ysrc, NB, static_cast<const float4*>(FT), kt2, sink);
+    adj_wave_tile<MT>(ysrc, NB, FT, kt2, sink);
+}
+
+template <class Tab>
+__device__ __forceinline__ Tab tab_global(const void* p) {
+  return Tab{static_cast<const char*>(p)};
 }
 
 }  // namespace pftpie

@@ -83,6 +83,8 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
   p->mt = ceil16(m);
   p->fa_ctiles = fa_ctiles_for(p->mt);
   p->fwd_ct = fwd_ct_default(p->mt);
+  p->use_lds = 1;
+  if (const char* env = std::getenv("PFTPIE_LDS")) p->use_lds = std::atoi(env) != 0;  // tuning override
   if (const char* env = std::getenv("PFTPIE_FWD_CT")) {  // tuning override
     const int ct = std::atoi(env);
     if (fwd_ct_valid(p->mt, ct)) p->fwd_ct = ct;
@@ -92,6 +94,8 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
     delete p;
     return hip_fail(e, "plan_create: hipGetDevice");
   }
+  e = hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess || p->num_cu < 1) p->num_cu = 256;
   std::vector<float> fa, ft;
   std::vector<uint16_t> fa16, ft16;
   const void* fa_src;
