@@ -82,6 +82,18 @@ pftpie_status pftpie_plan_destroy(pftpie_plan plan);
 pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,
                                pftpie_precision* prec);
 
+/* Autotuner: times the plan's candidate tile splits (forward column tiles
+ * per wave, LDS-resident or L2-resident twiddle tables for both directions)
+ * on a zero-filled scratch batch of `sample` patches and keeps the fastest.
+ * Allocates and frees scratch memory and synchronises the device; call it
+ * before the plan is used from other threads or streams (it changes the
+ * plan's launch choices, never its results' definition).  best_ms (may be
+ * NULL) receives the best forward + adjoint time per call in milliseconds.
+ * The environment variable PFTPIE_TUNE_CACHE names a text file in which
+ * results are looked up and recorded (keyed by device name, n, m and
+ * precision). */
+pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* best_ms);
+
 /* Forward: y_b = F_m psi_b F_m^T for b < batch.
  *   psi: device complex64 [batch][n][n]; y: device complex64 [batch][m][m].
  *   batch >= 0 (0 enqueues nothing).  psi and y must not overlap and must be

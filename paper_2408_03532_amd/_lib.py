@@ -40,6 +40,7 @@ SIGNATURES = {
     "pftpie_plan_create": (i32, [i32, i32, i32, ctypes.POINTER(c_plan)]),
     "pftpie_plan_destroy": (i32, [c_plan]),
     "pftpie_plan_info": (i32, [c_plan, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+    "pftpie_plan_autotune": (i32, [c_plan, i64, ctypes.POINTER(ctypes.c_double)]),
     "pft2d_forward": (i32, [c_plan, vp, vp, i64, vp]),
     "pft2d_adjoint": (i32, [c_plan, vp, vp, i64, vp]),
     "pftpie_group_create": (i32, [ctypes.POINTER(c_plan), i32, ctypes.POINTER(Desc), i64, i64, i64, i32,

@@ -36,7 +36,8 @@ struct pftpie_plan_s {
   int nb, mt;        // ceil(n/16), ceil(m/16)
   int fa_ctiles;     // column tiles allocated in FA (covers every forward split)
   int fwd_ct;        // forward column tiles per wave
-  int use_lds;       // persistent LDS-table kernels for the plain transforms
+  int use_lds;       // persistent LDS-table kernel for the plain forward
+  int use_lds_adj;   // persistent LDS-table kernel for the plain adjoint
   int num_cu;        // compute units of the plan's device
   int device;
   void* fa;          // device FA table (float4 blocks, or split 16-bit blocks)

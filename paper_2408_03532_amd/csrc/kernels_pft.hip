@@ -192,7 +192,7 @@ hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, 
 
 template <int MT>
 static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch, hipStream_t st) {
-  if (p->use_lds && p->ft_bytes <= kMaxLdsTable) {
+  if (p->use_lds_adj && p->ft_bytes <= kMaxLdsTable) {
     const int64_t items = batch * p->nb;
     if (p->prec == PFTPIE_SPLIT_BF16)
       return launch_lds(k_adjoint_lds<PrecBF16, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);

@@ -1,6 +1,8 @@
 // C ABI: plans, validation, error plumbing and dispatch of the partial
 // transform.  Every argument check happens here, on the host, before any
 // work is enqueued.
+#include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -84,7 +86,8 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
   p->fa_ctiles = fa_ctiles_for(p->mt);
   p->fwd_ct = fwd_ct_default(p->mt);
   p->use_lds = 1;
-  if (const char* env = std::getenv("PFTPIE_LDS")) p->use_lds = std::atoi(env) != 0;  // tuning override
+  p->use_lds_adj = 1;
+  if (const char* env = std::getenv("PFTPIE_LDS")) p->use_lds = p->use_lds_adj = std::atoi(env) != 0;
   if (const char* env = std::getenv("PFTPIE_FWD_CT")) {  // tuning override
     const int ct = std::atoi(env);
     if (fwd_ct_valid(p->mt, ct)) p->fwd_ct = ct;
@@ -166,6 +169,109 @@ pftpie_status pft2d_adjoint(pftpie_plan plan, const void* y, void* psi, int64_t 
   hipError_t e = launch_adjoint(plan, static_cast<const float2*>(y), static_cast<float2*>(psi), batch,
                                 static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pft2d_adjoint: launch");
+}
+
+pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* best_ms) {
+  if (pftpie_status s = check_plan(plan)) return s;
+  if (sample < 1 || sample > 1 << 20) return fail(PFTPIE_E_INVALID, "plan_autotune: need 1 <= sample <= 2^20");
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, plan->device);
+  if (e != hipSuccess) return hip_fail(e, "plan_autotune: device properties");
+  const std::string key = std::string(prop.gcnArchName) + " " + std::to_string(plan->n) + " " +
+                          std::to_string(plan->m) + " " + std::to_string((int)plan->prec);
+  const char* cache = std::getenv("PFTPIE_TUNE_CACHE");
+  if (cache) {  // "<arch> <n> <m> <prec> <fwd_ct> <lds_fwd> <lds_adj> <ms>" per line
+    if (FILE* f = std::fopen(cache, "r")) {
+      char arch[128];
+      int n, m, pr, ct, lf, la;
+      double ms;
+      while (std::fscanf(f, "%127s %d %d %d %d %d %d %lf", arch, &n, &m, &pr, &ct, &lf, &la, &ms) == 8) {
+        const std::string k2 = std::string(arch) + " " + std::to_string(n) + " " + std::to_string(m) + " " +
+                               std::to_string(pr);
+        if (k2 == key && fwd_ct_valid(plan->mt, ct)) {
+          plan->fwd_ct = ct;
+          plan->use_lds = lf;
+          plan->use_lds_adj = la;
+          if (best_ms) *best_ms = ms;
+          std::fclose(f);
+          return PFTPIE_OK;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  const size_t nin = (size_t)sample * plan->n * plan->n, nout = (size_t)sample * plan->m * plan->m;
+  float2 *x = nullptr, *y = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipMalloc((void**)&x, nin * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&y, nout * 8);
+  if (e == hipSuccess) e = hipMemset(x, 0, nin * 8);
+  if (e == hipSuccess) e = hipMemset(y, 0, nout * 8);
+  if (e == hipSuccess) e = hipStreamCreate(&st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(x);
+    (void)hipFree(y);
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(PFTPIE_E_NOMEM, std::string("plan_autotune: scratch: ") + hipGetErrorString(e));
+  }
+  auto time_ms = [&](bool fwd) -> double {
+    double best = 1e30;
+    for (int rep = 0; rep < 4; ++rep) {
+      (void)hipEventRecord(e0, st);
+      hipError_t le = fwd ? launch_forward(plan, x, y, sample, st) : launch_adjoint(plan, y, x, sample, st);
+      (void)hipEventRecord(e1, st);
+      if (le != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, (double)ms);  // first run warms up
+    }
+    return best;
+  };
+  double best_f = 1e30, best_a = 1e30;
+  int best_ct = plan->fwd_ct, best_lf = plan->use_lds, best_la = plan->use_lds_adj;
+  for (int ct = 1; ct <= 4; ++ct) {
+    if (!fwd_ct_valid(plan->mt, ct)) continue;
+    for (int lf = 1; lf >= 0; --lf) {
+      plan->fwd_ct = ct;
+      plan->use_lds = lf;
+      const double t = time_ms(true);
+      if (t < best_f) {
+        best_f = t;
+        best_ct = ct;
+        best_lf = lf;
+      }
+    }
+  }
+  for (int la = 1; la >= 0; --la) {
+    plan->use_lds_adj = la;
+    const double t = time_ms(false);
+    if (t < best_a) {
+      best_a = t;
+      best_la = la;
+    }
+  }
+  plan->fwd_ct = best_ct;
+  plan->use_lds = best_lf;
+  plan->use_lds_adj = best_la;
+  cleanup();
+  if (best_f >= 1e30 || best_a >= 1e30) return fail(PFTPIE_E_DEVICE, "plan_autotune: every candidate failed");
+  if (best_ms) *best_ms = best_f + best_a;
+  if (cache) {
+    if (FILE* f = std::fopen(cache, "a")) {
+      std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", prop.gcnArchName, plan->n, plan->m, (int)plan->prec, best_ct,
+                   best_lf, best_la, best_f + best_a);
+      std::fclose(f);
+    }
+  }
+  return PFTPIE_OK;
 }
 
 }  // extern "C"

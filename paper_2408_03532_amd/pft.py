@@ -144,3 +144,65 @@ def pft2d(psi, m, precision="fp32"):
 def pft2d_adj(y, n, precision="fp32"):
     """Differentiable adjoint (backward = forward)."""
     return _PFT2DAdjoint.apply(y, n, precision)
+
+
+def autotune(plan, sample=256):
+    """Time the plan's candidate tile splits on a scratch batch and keep the
+    fastest (see pftpie_plan_autotune).  Returns the best forward + adjoint
+    milliseconds per call of `sample` patches."""
+    ms = ctypes.c_double()
+    with torch.cuda.device(plan.device):
+        _lib.call("pftpie_plan_autotune", plan.handle, int(sample), ctypes.byref(ms))
+    return ms.value
+
+
+class Group:
+    """An uneven batch: descriptors (n, m, in_offset, out_offset) over packed
+    complex64 arrays, run as one persistent launch (replayed as a hipGraph).
+
+    descs: int array [count][4]; offsets in complex elements.  For the
+    forward, input blocks hold n*n and output blocks m*m elements; with
+    adjoint=True the reverse.  All descriptors' (n, m) pairs get a plan of
+    the given precision."""
+
+    def __init__(self, descs, in_len, out_len, precision="fp32", adjoint=False, device=None):
+        import numpy as np
+        d = np.asarray(descs, dtype=np.int64).reshape(-1, 4)
+        self.count, self.in_len, self.out_len = len(d), int(in_len), int(out_len)
+        self.adjoint, self.precision = bool(adjoint), precision
+        pairs = sorted({(int(n), int(m)) for n, m in d[:, :2]}) if len(d) else []
+        self.plans = [get_plan(n, m, precision, device) for n, m in pairs]
+        self.device = self.plans[0].device if self.plans else torch.device("cuda", torch.cuda.current_device())
+        arr = (_lib.c_plan * max(1, len(self.plans)))(*[p.handle for p in self.plans])
+        darr = (_lib.Desc * max(1, self.count))()
+        for i, (n, m, io, oo) in enumerate(d):
+            darr[i] = _lib.Desc(int(n), int(m), int(io), int(oo))
+        h = _lib.c_group()
+        with torch.cuda.device(self.device):
+            _lib.call("pftpie_group_create", arr, len(self.plans), darr, self.count, self.in_len, self.out_len,
+                      int(self.adjoint), ctypes.byref(h))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().pftpie_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, inp, out=None):
+        _require(inp, "inp")
+        if inp.numel() != self.in_len:
+            raise ValueError(f"inp must hold {self.in_len} complex elements")
+        if out is None:
+            out = torch.zeros(self.out_len, dtype=torch.complex64, device=inp.device)
+        _require(out, "out")
+        if out.numel() != self.out_len:
+            raise ValueError(f"out must hold {self.out_len} complex elements")
+        _lib.call("pft2d_group_run", self.handle, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                  _stream_ptr(inp))
+        return out

@@ -1,0 +1,124 @@
+"""GPU parity of the uneven batch (one persistent launch over descriptors of
+different sizes, replayed as a hipGraph) against the FP64 oracle, and of the
+plan autotuner (it changes launch choices, never results)."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import pft as opft
+
+pytestmark = pytest.mark.gpu
+
+TOLS = {"fp32": 1e-5, "split_bf16": 1e-4, "split_fp16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2408_03532_amd as p
+    p.lib()
+    return p
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def mixed_descs(sizes, seed=0, pad=0):
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(len(sizes))
+    d, io, oo = [], 0, 0
+    for k in order:
+        n, m = sizes[k]
+        d.append((n, m, io, oo))
+        io += n * n + pad
+        oo += m * m + pad
+    return np.array(d, dtype=np.int64), io, oo
+
+
+SMALL = [(16, 4)] * 5 + [(40, 10)] * 4 + [(64, 16)] * 6 + [(128, 32)] * 3 + [(48, 48)] * 2 + [(256, 64)] * 2
+
+
+@pytest.mark.parametrize("prec", sorted(TOLS))
+def test_small_mixed_forward_and_adjoint(pk, prec):
+    d, tin, tout = mixed_descs(SMALL, pad=2)
+    x = workloads.grouped_inputs(d, tin, seed=7)
+    g = pk.Group(d, tin, tout, prec)
+    y = g.run(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = opft.grouped_forward(d, x, tout)
+    for n, m, io, oo in d:
+        assert rel(y[oo:oo + m * m], ref[oo:oo + m * m]) <= TOLS[prec] * 3
+    assert rel(y, ref) <= TOLS[prec]
+    da = workloads.adjoint_descs(d)
+    ya = workloads.grouped_inputs(da, tout, seed=8, adjoint=True)
+    ga = pk.Group(da, tout, tin, prec, adjoint=True)
+    xa = ga.run(torch.from_numpy(ya).cuda()).cpu().numpy()
+    refa = opft.grouped_adjoint(da, ya, tin)
+    assert rel(xa, refa) <= TOLS[prec]
+
+
+def test_graph_replay_with_new_buffers_and_without_graph(pk, monkeypatch):
+    d, tin, tout = mixed_descs(SMALL, seed=3)
+    x1 = workloads.grouped_inputs(d, tin, seed=1)
+    x2 = workloads.grouped_inputs(d, tin, seed=2)
+    g = pk.Group(d, tin, tout)
+    a = torch.from_numpy(x1).cuda()
+    b = torch.from_numpy(x2).cuda()
+    outs = [g.run(a), g.run(b), g.run(a)]
+    torch.cuda.synchronize()
+    r1 = opft.grouped_forward(d, x1, tout)
+    r2 = opft.grouped_forward(d, x2, tout)
+    assert rel(outs[0].cpu().numpy(), r1) <= 1e-5
+    assert rel(outs[1].cpu().numpy(), r2) <= 1e-5
+    assert torch.equal(outs[0], outs[2])
+    monkeypatch.setenv("PFTPIE_GROUP_GRAPH", "0")
+    g2 = pk.Group(d, tin, tout)
+    assert torch.equal(g2.run(a), outs[0])
+
+
+@pytest.mark.parametrize("prec", sorted(TOLS))
+def test_uneven_workload_full_size_sampled(pk, prec):
+    """8192 descriptors, n in {64, 128, 256, 512} in equal shares, m = n/4;
+    8 sampled descriptors per size checked against the oracle."""
+    print("group full", prec, flush=True)
+    d, tin, tout = workloads.grouped_descs()
+    rng = np.random.default_rng(11)
+    idx = np.concatenate([rng.choice(np.nonzero(d[:, 0] == s)[0], 8, replace=False) for s in workloads.GROUP_SIZES])
+    x = workloads.grouped_inputs(d, tin, idx=idx)        # only sampled blocks non-zero
+    xt = torch.from_numpy(x).cuda()
+    g = pk.Group(d, tin, tout, prec)
+    y = g.run(xt).cpu().numpy()
+    for i in idx:
+        n, m, io, oo = (int(v) for v in d[i])
+        ref = opft.forward(x[io:io + n * n].reshape(n, n), m)
+        assert rel(y[oo:oo + m * m].reshape(m, m), ref) <= TOLS[prec] * 3
+    others = np.setdiff1d(np.arange(len(d)), idx)[:64]
+    for i in others:                                      # zero blocks transform to zero
+        n, m, io, oo = (int(v) for v in d[i])
+        assert not np.any(y[oo:oo + m * m])
+
+
+def test_invalid_descriptors(pk):
+    d = np.array([(32, 8, 0, 0), (32, 8, 1024, 32)], dtype=np.int64)      # outputs overlap
+    with pytest.raises(pk.PftpieError, match="overlap"):
+        pk.Group(d, 2048, 128)
+    with pytest.raises(pk.PftpieError, match="outside"):
+        pk.Group(np.array([(32, 8, 1500, 0)]), 2048, 64)
+    g = pk.Group(np.array([(32, 8, 0, 0)]), 1024, 64)
+    with pytest.raises(ValueError):
+        g.run(torch.zeros(10, dtype=torch.complex64, device="cuda"))
+
+
+def test_autotuner_keeps_results(pk, tmp_path, monkeypatch):
+    monkeypatch.setenv("PFTPIE_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    plan = pk.Plan(128, 32)
+    x = torch.from_numpy(workloads.pft_patches(128, range(8))).cuda()
+    before = plan.forward(x).cpu().numpy()
+    ms = pk.autotune(plan, 64)
+    assert ms > 0
+    after = plan.forward(x).cpu().numpy()
+    assert rel(after, before) <= 1e-6
+    assert (tmp_path / "tune.txt").read_text().count("\n") == 1
+    plan2 = pk.Plan(128, 32)
+    assert pk.autotune(plan2, 64) == pytest.approx(ms)   # read back from the cache
