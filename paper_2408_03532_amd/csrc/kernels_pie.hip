@@ -1,19 +1,26 @@
 // PIE / ePIE sweep kernels (Sec. 2.1: projection eq. (3), objective eq. (4),
 // iterates eqs. (5)-(6)), built on the MFMA partial-transform engines.
 //
-// Per chunk of positions:
-//   k_pie_forward  gather psi = P * O[window] in the operand loader, forward
-//                  partial DFT, magnitude projection in the epilogue; writes
-//                  the residual r = u' - u ([chunk][m][m]) and per-wave
-//                  partial sums of (|u| - a)^2.
-//   k_pie_adjoint  dpsi = F^H r conj(F) / n^2, scattered in the epilogue:
-//                  O (or numO) += conj(P) dpsi, D += |P|^2 (double),
-//                  numP += conj(O_j) dpsi, E += |O_j|^2 (double).
-//   k_pie_max      max D (and max E) for the overlap-normalised step.
-//   k_pie_apply    O += beta numO / (D + alpha max D) (or beta numO), same
-//                  for P; clears the accumulators it read.
-// Per sweep: k_pie_begin (copy O, clear accumulators / stats) and
-// k_pie_stats (||dO||^2, ||O||^2, non-finite count, Phi).
+// Per chunk of positions (all seeing the object and probe of the chunk start):
+//   k_pie_forward   gathers psi = P * O[window] in the operand loader, runs
+//                   the forward transform (its row strips split over WR
+//                   waves, partial spectra summed through LDS) and applies the
+//                   magnitude projection in the epilogue: residual
+//                   r = u' - u ([chunk][m][m]) and per-wave sums of
+//                   (|u| - a)^2.
+//   k_pie_adjoint   dpsi = F^H r conj(F) / n^2.  A single-position chunk (the
+//                   sequential iterate of eq. (5)) updates O (and P) in place
+//                   in the epilogue: every pixel belongs to exactly one lane,
+//                   so no atomics.  Larger chunks store dpsi.
+//   k_pie_probe_gather   numP = sum_j conj(O_j) dpsi_j, E = sum_j |O_j|^2 per
+//                   probe pixel (ePIE, larger chunks).
+//   k_pie_object_gather  per 16 x 16 object tile, the positions of its cover
+//                   list that belong to the chunk contribute conj(P) dpsi_j
+//                   and |P|^2 (FP64); the plain step is applied at once, the
+//                   overlap-normalised one is stored with per-tile maxima.
+//   k_pie_reduce_max, k_pie_apply   maxima and the normalised updates.
+// Per sweep: k_pie_begin (object copy, ranks, clears) and the statistics
+// pair k_pie_stats_part / k_pie_stats_final (fixed-order sums).
 #include "internal.hpp"
 #include "pft_split.hpp"
 #include "pie.hpp"
@@ -30,18 +37,87 @@ __device__ __forceinline__ int pos_index(const int32_t* __restrict__ order, int 
   return ok ? j : 0;
 }
 
-template <class PR, int MT, int CT, bool EXACT>
-__global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieArgs a, int c0) {
+// Gather source that also tracks max |P|^2 and max |O|^2 over what it reads.
+template <bool EXACT>
+struct GatherTrackSrc {
+  GatherSrc<EXACT> g;
+  mutable float mp, mo;
+  __device__ __forceinline__ c4 load(int row, int col0) const {
+    c4 v;
+    const float2* orow = g.O + (size_t)(g.r + row) * g.W + g.c + col0;
+    const float2* prow = g.P + (size_t)row * g.n + col0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = col0 + s;
+      if (EXACT || (row < g.n && col < g.n)) {
+        const float2 p = prow[s], o = orow[s];
+        mp = fmaxf(mp, p.x * p.x + p.y * p.y);
+        mo = fmaxf(mo, o.x * o.x + o.y * o.y);
+        v.v[s] = cmul(p, o);
+      } else {
+        v.v[s] = make_float2(0.f, 0.f);
+      }
+    }
+    return v;
+  }
+};
+
+// Forward + projection.  Block = WR x WC waves: wave (wr, wc) runs strips
+// wr, wr + WR, ... for column-tile group wc; partial spectra of wr > 0 are
+// added to wr = 0 through LDS, whose waves then apply the projection.
+template <class PR, int MT, int CT, int WR, bool EXACT, bool TRACK>
+__global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(PieArgs a, int c0) {
+  constexpr int WC = (MT + CT - 1) / CT;
   const int q = blockIdx.x;
   bool valid;
   const int j = pos_index(a.order, a.J, c0, q, &valid);
   const int w = threadIdx.x >> 6;
-  const int c2t0 = w * CT;
+  const int wc = w % WC, wr = w / WC;
+  const int c2t0 = wc * CT;
   const int2 ps = a.pos[j];
-  GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
-  f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim);
   const int lane = lane_id();
+  f32x4 Yre[MT][CT], Yim[MT][CT];
+  if constexpr (TRACK) {
+    GatherTrackSrc<EXACT> src{{a.O, a.P, a.W, a.n, ps.x, ps.y}, 0.f, 0.f};
+    fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, wr, WR);
+    if (wc == 0) {
+      const float mp = wave_max(src.mp), mo = wave_max(src.mo);
+      if (lane == 0 && valid) {
+        atomicMax(&a.winmax[2 * j], __float_as_uint(mp));
+        atomicMax(&a.winmax[2 * j + 1], __float_as_uint(mo));
+      }
+    }
+  } else {
+    GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
+    fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, wr, WR);
+  }
+  if constexpr (WR > 1) {
+    // partial spectra: [WR - 1][WC][MT * CT * 2][64 lanes] f32x4
+    __shared__ f32x4 part[(WR - 1) * WC * MT * CT * 2 * 64];
+    if (wr > 0) {
+      f32x4* dst = part + ((size_t)((wr - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+      for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+        for (int b1 = 0; b1 < CT; ++b1) {
+          dst[((a1 * CT + b1) * 2 + 0) * 64 + lane] = Yre[a1][b1];
+          dst[((a1 * CT + b1) * 2 + 1) * 64 + lane] = Yim[a1][b1];
+        }
+    }
+    __syncthreads();
+    if (wr > 0) return;
+#pragma unroll
+    for (int r = 1; r < WR; ++r) {
+      const f32x4* src = part + ((size_t)((r - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+      for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+        for (int b1 = 0; b1 < CT; ++b1) {
+          Yre[a1][b1] += src[((a1 * CT + b1) * 2 + 0) * 64 + lane];
+          Yim[a1][b1] += src[((a1 * CT + b1) * 2 + 1) * 64 + lane];
+        }
+    }
+  }
   const int m = a.m;
   const float* amp = a.amp + (size_t)j * m * m;
   float2* res = a.R + (size_t)q * m * m;
@@ -65,7 +141,7 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieAr
             const float s = av / mag - 1.f;  // a u/|u| - u = (a/|u| - 1) u
             r = make_float2(s * ur, s * ui);
           } else {
-            r = make_float2(av - ur, -ui);    // theta(0) = 0
+            r = make_float2(av - ur, -ui);  // theta(0) = 0
           }
           res[(size_t)c1 * m + c2] = r;
           const double d = (double)mag - (double)av;
@@ -74,22 +150,37 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_pie_forward(PieAr
       }
     }
   phi = wave_sum(phi);
-  if (lane == 0 && valid) a.phi_part[(size_t)j * 4 + w] = phi;
+  if (lane == 0 && valid) a.phi_part[(size_t)j * 4 + wc] = phi;
 }
 
-// Scatter of dpsi = X / n^2 for one finished 16 x 16 tile.  Holds copies of
-// the fields it needs (never the address of a kernel argument).
-struct ScatterSink {
+// Residual source of the adjoint (m x m, masked).
+struct ResSrc {
+  const float2* __restrict__ p;
+  int m;
+  __device__ __forceinline__ c4 load(int row, int col0) const {
+    c4 v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = col0 + s;
+      v.v[s] = (row < m && col < m) ? p[(size_t)row * m + col] : make_float2(0.f, 0.f);
+    }
+    return v;
+  }
+};
+
+// Single-position chunk: O[window] += beta conj(P) dpsi / (|P|^2 + alpha max |P|^2)
+// (denominator only with norm), and with a probe step
+// P += gamma conj(O_j) dpsi / (|O_j|^2 + alpha max |O_j|^2), both from the
+// values before this position's update.  Each pixel belongs to one lane.
+struct UpdateSink {
   float2* __restrict__ O;
-  const float2* __restrict__ P;
-  float2* __restrict__ numO;
-  double* __restrict__ D;
-  float2* __restrict__ numP;
-  double* __restrict__ E;
-  int n, W, r, c, mode, norm, probe_step;
-  float inv, beta;
+  float2* __restrict__ P;
+  int n, W, r, c, norm, probe_step, valid;
+  float inv, beta, gamma;
+  double regP, regO;  // alpha * max |P|^2, alpha * max |O_j|^2
   template <bool TR>
   __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
+    if (!valid) return;
     const int lane = lane_id();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -97,118 +188,191 @@ struct ScatterSink {
       const int k1 = rc.x, k2 = rc.y;
       if (k1 < n && k2 < n) {
         const float2 d = make_float2(xre[i] * inv, xim[i] * inv);
-        const float2 p = P[(size_t)k1 * n + k2];
+        const size_t pi = (size_t)k1 * n + k2;
         const size_t o = (size_t)(r + k1) * W + (c + k2);
-        const float2 v = cmulc(p, d);  // conj(P) dpsi
-        if (mode == kModeDirect) {
-          unsafeAtomicAdd(&O[o].x, beta * v.x);
-          unsafeAtomicAdd(&O[o].y, beta * v.y);
-        } else {
-          unsafeAtomicAdd(&numO[o].x, v.x);
-          unsafeAtomicAdd(&numO[o].y, v.y);
-          if (norm) unsafeAtomicAdd(&D[o], (double)p.x * p.x + (double)p.y * p.y);
-          if (probe_step) {
-            const float2 ob = O[o];   // unchanged until the apply pass
-            const float2 vp = cmulc(ob, d);  // conj(O_j) dpsi
-            const size_t pi = (size_t)k1 * n + k2;
-            unsafeAtomicAdd(&numP[pi].x, vp.x);
-            unsafeAtomicAdd(&numP[pi].y, vp.y);
-            if (norm) unsafeAtomicAdd(&E[pi], (double)ob.x * ob.x + (double)ob.y * ob.y);
+        const float2 p = P[pi];
+        const float2 ov = O[o];
+        float so = beta;
+        if (norm) {
+          const double p2 = (double)p.x * p.x + (double)p.y * p.y;
+          so = p2 > 0.0 ? (float)((double)beta / (p2 + regP)) : 0.f;
+        }
+        const float2 vo = cmulc(p, d);
+        O[o] = make_float2(ov.x + so * vo.x, ov.y + so * vo.y);
+        if (probe_step) {
+          float sp = gamma;
+          if (norm) {
+            const double o2 = (double)ov.x * ov.x + (double)ov.y * ov.y;
+            sp = o2 > 0.0 ? (float)((double)gamma / (o2 + regO)) : 0.f;
           }
+          const float2 vp = cmulc(ov, d);
+          P[pi] = make_float2(p.x + sp * vp.x, p.y + sp * vp.y);
         }
       }
     }
   }
 };
 
-template <class PR, int MT>
+// Larger chunks: store dpsi = X / n^2.
+struct DeltaSink {
+  float2* __restrict__ out;
+  int n;
+  float inv;
+  template <bool TR>
+  __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
+    const int lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int2 rc = tile_rc<TR>(k1t, k2t, i, lane);
+      if (rc.x < n && rc.y < n) out[(size_t)rc.x * n + rc.y] = make_float2(xre[i] * inv, xim[i] * inv);
+    }
+  }
+};
+
+template <class PR, int MT, bool SINGLE>
 __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
   const int q = blockIdx.x;
-  const int j = pos_index(a.order, a.J, c0, q, nullptr);
+  bool valid;
+  const int j = pos_index(a.order, a.J, c0, q, &valid);
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int2 ps = a.pos[j];
-  struct ResSrc {
-    const float2* __restrict__ p;
-    int m;
-    __device__ __forceinline__ c4 load(int row, int col0) const {
-      c4 v;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int col = col0 + s;
-        v.v[s] = (row < m && col < m) ? p[(size_t)row * m + col] : make_float2(0.f, 0.f);
-      }
-      return v;
+  ResSrc src{a.R + (size_t)q * a.m * a.m, a.m};
+  const TabG T{static_cast<const char*>(a.ft)};
+  if constexpr (SINGLE) {
+    const int2 ps = a.pos[j];
+    double regP = 0.0, regO = 0.0;
+    if (a.norm) {
+      regP = a.alpha * (double)__uint_as_float(a.winmax[2 * j]);
+      regO = a.alpha * (double)__uint_as_float(a.winmax[2 * j + 1]);
     }
-  } src{a.R + (size_t)q * a.m * a.m, a.m};
-  ScatterSink sink{a.O, a.P, a.numO, a.D, a.numP, a.E, a.n, a.W, ps.x, ps.y,
-                   a.mode, a.norm, a.probe_step, a.inv_n2, a.beta};
-  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, TabG{static_cast<const char*>(a.ft)}, kt2, sink);
+    UpdateSink sink{a.O, a.P, a.n, a.W, ps.x, ps.y, a.norm, a.probe_step, (int)valid,
+                    a.inv_n2, a.beta, a.gamma, regP, regO};
+    for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+  } else {
+    DeltaSink sink{a.dpsi + (size_t)q * a.n * a.n, a.n, a.inv_n2};
+    for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// element-wise passes
+// gathers of a chunk's corrections
 
-// Region of one apply pass: the window of the single position of a chunk
-// (read on the device), or the scan's bounding box.
-struct Region {
-  int r0, c0, h, w;
-};
-
-__device__ __forceinline__ Region region_of(const PieArgs& a, int chunk0, int single) {
-  if (single) {
-    const int j = pos_index(a.order, a.J, chunk0, 0, nullptr);
-    const int2 ps = a.pos[j];
-    return {ps.x, ps.y, a.n, a.n};
-  }
-  return {a.bb_r0, a.bb_c0, a.bb_h, a.bb_w};
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, sh[k]);
+  return r;
 }
 
-__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
-
-// max over the region of D (and over the probe of E) -> a.maxes[0], [1]
-// (non-negative doubles compare like their bit patterns).
-__global__ __launch_bounds__(256) void k_pie_max(PieArgs a, int chunk0, int single) {
-  const Region rg = region_of(a, chunk0, single);
-  const size_t total = (size_t)rg.h * rg.w;
-  double mD = 0.0, mE = 0.0;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    const int rr = (int)(t / rg.w), cc = (int)(t % rg.w);
-    mD = fmax(mD, a.D[(size_t)(rg.r0 + rr) * a.W + rg.c0 + cc]);
-  }
-  if (a.probe_step) {
-    const size_t nn = (size_t)a.n * a.n;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < nn; t += (size_t)gridDim.x * blockDim.x)
-      mE = fmax(mE, a.E[t]);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    mD = fmax(mD, __shfl_xor(mD, off, 64));
-    mE = fmax(mE, __shfl_xor(mE, off, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(reinterpret_cast<unsigned long long*>(&a.maxes[0]), dbits(mD));
-    atomicMax(reinterpret_cast<unsigned long long*>(&a.maxes[1]), dbits(mE));
-  }
-}
-
-__global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int chunk0, int single) {
-  const Region rg = region_of(a, chunk0, single);
-  const size_t total = (size_t)rg.h * rg.w;
-  const double regO = a.alpha * a.maxes[0];
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    const int rr = (int)(t / rg.w), cc = (int)(t % rg.w);
-    const size_t o = (size_t)(rg.r0 + rr) * a.W + rg.c0 + cc;
-    const float2 num = a.numO[o];
-    float sc = a.beta;
-    if (a.norm) {
-      const double d = a.D[o];
-      sc = (d > 0.0) ? (float)((double)a.beta / (d + regO)) : 0.f;
-      a.D[o] = 0.0;
+// Per probe pixel: numP = sum_q conj(O_j) dpsi_q, E = sum_q |O_j|^2 over the
+// chunk (O as at the chunk start).  Stores both and per-block maxima of E.
+__global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int cnt) {
+  __shared__ double sh[4];
+  const size_t nn = (size_t)a.n * a.n;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (k < nn) {
+    const int k1 = (int)(k / a.n), k2 = (int)(k % a.n);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int q = 0; q < cnt; ++q) {
+      bool valid;
+      const int j = pos_index(a.order, a.J, c0, q, &valid);
+      if (!valid) continue;
+      const int2 ps = a.pos[j];
+      const float2 o = a.O[(size_t)(ps.x + k1) * a.W + ps.y + k2];
+      const float2 d = a.dpsi[(size_t)q * nn + k];
+      const float2 v = cmulc(o, d);
+      acc.x += v.x;
+      acc.y += v.y;
+      e += (double)o.x * o.x + (double)o.y * o.y;
     }
-    float2 ov = a.O[o];
-    ov.x += sc * num.x;
-    ov.y += sc * num.y;
-    a.O[o] = ov;
-    a.numO[o] = make_float2(0.f, 0.f);
+    a.numP[k] = acc;
+    if (a.norm) a.E[k] = e;
+  }
+  if (a.norm) {
+    const double mx = block_max(e, sh);
+    if (threadIdx.x == 0) a.maxpart[a.tiles_x * a.tiles_y + blockIdx.x] = mx;
+  }
+}
+
+// Per 16 x 16 object tile of the bounding box: sum over the chunk's positions
+// in the tile's cover list.  norm 0: O += beta numO at once; norm 1: store
+// numO and D with the tile's maximum of D.
+__global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, int cnt) {
+  __shared__ double sh[4];
+  const int tile = blockIdx.x;
+  const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
+  const int py = a.bb_r0 + ty * 16 + (threadIdx.x >> 4);
+  const int px = a.bb_c0 + tx * 16 + (threadIdx.x & 15);
+  const bool inside = (py < a.bb_r0 + a.bb_h) && (px < a.bb_c0 + a.bb_w);
+  const size_t nn = (size_t)a.n * a.n;
+  float2 acc = make_float2(0.f, 0.f);
+  double D = 0.0;
+  const int e0 = a.tile_ptr[tile], e1 = a.tile_ptr[tile + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = a.tile_pos[e];
+    const int q = a.rank[j] - c0;
+    if (q < 0 || q >= cnt) continue;
+    const int2 ps = a.pos[j];
+    const int dy = py - ps.x, dx = px - ps.y;
+    if (!inside || dy < 0 || dy >= a.n || dx < 0 || dx >= a.n) continue;
+    const size_t k = (size_t)dy * a.n + dx;
+    const float2 p = a.P[k];
+    const float2 d = a.dpsi[(size_t)q * nn + k];
+    const float2 v = cmulc(p, d);
+    acc.x += v.x;
+    acc.y += v.y;
+    D += (double)p.x * p.x + (double)p.y * p.y;
+  }
+  const size_t o = (size_t)py * a.W + px;
+  if (!a.norm) {
+    if (inside && (acc.x != 0.f || acc.y != 0.f)) {
+      const float2 ov = a.O[o];
+      a.O[o] = make_float2(ov.x + a.beta * acc.x, ov.y + a.beta * acc.y);
+    }
+    return;
+  }
+  if (inside) {
+    a.numO[o] = acc;
+    a.D[o] = D;
+  }
+  const double mx = block_max(inside ? D : 0.0, sh);
+  if (threadIdx.x == 0) a.maxpart[tile] = mx;
+}
+
+// maxes[0] = max D over the tile maxima, maxes[1] = max E over the probe blocks.
+__global__ __launch_bounds__(1024) void k_pie_reduce_max(PieArgs a, int nprobe_blocks) {
+  __shared__ double sh[16];
+  const int ntiles = a.tiles_x * a.tiles_y;
+  double mD = 0.0, mE = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) mD = fmax(mD, a.maxpart[t]);
+  for (int t = threadIdx.x; t < nprobe_blocks; t += blockDim.x) mE = fmax(mE, a.maxpart[ntiles + t]);
+  mD = block_max(mD, sh);
+  __syncthreads();
+  mE = block_max(mE, sh);
+  if (threadIdx.x == 0) {
+    a.maxes[0] = mD;
+    a.maxes[1] = mE;
+  }
+}
+
+// Normalised object update over the bounding box and the probe update.
+__global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
+  if (object_part) {
+    const size_t total = (size_t)a.bb_h * a.bb_w;
+    const double regO = a.alpha * a.maxes[0];
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+      const int rr = (int)(t / a.bb_w), cc = (int)(t % a.bb_w);
+      const size_t o = (size_t)(a.bb_r0 + rr) * a.W + a.bb_c0 + cc;
+      const double d = a.D[o];
+      if (d > 0.0) {
+        const float sc = (float)((double)a.beta / (d + regO));
+        const float2 num = a.numO[o];
+        const float2 ov = a.O[o];
+        a.O[o] = make_float2(ov.x + sc * num.x, ov.y + sc * num.y);
+      }
+    }
   }
   if (a.probe_step) {
     const size_t nn = (size_t)a.n * a.n;
@@ -219,42 +383,35 @@ __global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int chunk0, int si
       if (a.norm) {
         const double e = a.E[t];
         sc = (e > 0.0) ? (float)((double)a.gamma / (e + regP)) : 0.f;
-        a.E[t] = 0.0;
       }
-      float2 pv = a.P[t];
-      pv.x += sc * num.x;
-      pv.y += sc * num.y;
-      a.P[t] = pv;
-      a.numP[t] = make_float2(0.f, 0.f);
+      const float2 pv = a.P[t];
+      a.P[t] = make_float2(pv.x + sc * num.x, pv.y + sc * num.y);
     }
   }
 }
 
-__global__ void k_pie_clear_max(PieArgs a) {
-  if (threadIdx.x < 2) a.maxes[threadIdx.x] = 0.0;
-}
-
-// Sweep start: O0 = O; clear the object and probe accumulators and stats.
+// Sweep start: O0 = O, ranks of the sweep order, cleared per-position slots.
 __global__ __launch_bounds__(256) void k_pie_begin(PieArgs a) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t total = (size_t)a.H * a.W;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    a.O0[t] = a.O[t];
-    if (a.numO) a.numO[t] = make_float2(0.f, 0.f);
-    if (a.D) a.D[t] = 0.0;
+  for (size_t t = t0; t < total; t += stride) a.O0[t] = a.O[t];
+  for (size_t t = t0; t < (size_t)a.J; t += stride) {
+    if (a.order) {
+      const int j = a.order[t];
+      if (j >= 0 && j < a.J) a.rank[j] = (int)t;
+    } else {
+      a.rank[t] = (int)t;
+    }
+    a.winmax[2 * t] = 0u;
+    a.winmax[2 * t + 1] = 0u;
   }
-  const size_t nn = (size_t)a.n * a.n;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < nn; t += (size_t)gridDim.x * blockDim.x) {
-    if (a.numP) a.numP[t] = make_float2(0.f, 0.f);
-    if (a.E) a.E[t] = 0.0;
-  }
-  const size_t np = (size_t)a.J * 4;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < np; t += (size_t)gridDim.x * blockDim.x)
-    a.phi_part[t] = 0.0;
-  if (blockIdx.x == 0 && threadIdx.x < 4) a.stats[threadIdx.x] = 0.0;
+  for (size_t t = t0; t < (size_t)a.J * 4; t += stride) a.phi_part[t] = 0.0;
 }
 
-// Sweep end: stats = {Phi, ||O - O0||^2, ||O0||^2, non-finite count}.
-__global__ __launch_bounds__(256) void k_pie_stats(PieArgs a) {
+// Statistics partials per block: ||O - O0||^2, ||O0||^2, non-finite count.
+__global__ __launch_bounds__(256) void k_pie_stats_part(PieArgs a) {
+  __shared__ double sh[3][4];
   const size_t total = (size_t)a.H * a.W;
   double d2 = 0.0, o2 = 0.0, bad = 0.0;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
@@ -274,20 +431,33 @@ __global__ __launch_bounds__(256) void k_pie_stats(PieArgs a) {
   d2 = wave_sum(d2);
   o2 = wave_sum(o2);
   bad = wave_sum(bad);
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    unsafeAtomicAdd(&a.stats[1], d2);
-    unsafeAtomicAdd(&a.stats[2], o2);
-    unsafeAtomicAdd(&a.stats[3], bad);
+    sh[0][w] = d2;
+    sh[1][w] = o2;
+    sh[2][w] = bad;
   }
-  if (blockIdx.x == 0) {
-    // Phi: the per-position partials summed in a fixed order by one wave
-    if (threadIdx.x < 64) {
-      const size_t np = (size_t)a.J * 4;
-      double s = 0.0;
-      for (size_t t = threadIdx.x; t < np; t += 64) s += a.phi_part[t];
-      s = wave_sum(s);
-      if (threadIdx.x == 0) unsafeAtomicAdd(&a.stats[0], s / ((double)a.J * a.n * a.n));
-    }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[threadIdx.x][k];
+    a.red[(size_t)blockIdx.x * 3 + threadIdx.x] = s;
+  }
+}
+
+// stats = {Phi, ||dO||^2, ||O||^2, non-finite}: one wave, fixed order.
+__global__ __launch_bounds__(64) void k_pie_stats_final(PieArgs a, int nblocks) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const size_t np = (size_t)a.J * 4;
+  for (size_t t = threadIdx.x; t < np; t += 64) v[0] += a.phi_part[t];
+  for (int b = threadIdx.x; b < nblocks; b += 64)
+    for (int c = 0; c < 3; ++c) v[c + 1] += a.red[(size_t)b * 3 + c];
+  for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
+  if (threadIdx.x == 0) {
+    a.stats[0] = v[0] / ((double)a.J * a.n * a.n);
+    a.stats[1] = v[1];
+    a.stats[2] = v[2];
+    a.stats[3] = v[3];
   }
 }
 
@@ -307,23 +477,43 @@ __global__ __launch_bounds__(256) void k_crop_amp(const float* __restrict__ I, i
 // ---------------------------------------------------------------------------
 // launch
 
-template <class PR, int MT, int CT>
+static int ew_blocks(size_t work) {
+  size_t b = (work + 255) / 256;
+  if (b > 4096) b = 4096;
+  return b < 1 ? 1 : (int)b;
+}
+
+// forward split: WR row groups so a chunk keeps the compute units busy, as
+// long as the partial spectra fit the LDS (WR - 1 copies of MT x MT tiles)
+template <int MT>
+constexpr int pie_wr() {
+  return MT <= 2 ? 4 : (MT <= 4 ? 2 : 1);
+}
+
+template <class PR, int MT, bool TRACK>
 static void fwd_launch(const PieArgs& a, int c0, int cnt, hipStream_t st) {
-  constexpr int W = (MT + CT - 1) / CT;
-  dim3 grid(cnt), block(64 * W);
+  constexpr int CT = (MT <= 2) ? MT : 2;
+  constexpr int WC = (MT + CT - 1) / CT;
+  constexpr int WR = pie_wr<MT>();
+  dim3 grid(cnt), block(64 * WR * WC);
   if (a.n % 16 == 0)
-    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, true>), grid, block, 0, st, a, c0);
+    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK>), grid, block, 0, st, a, c0);
   else
-    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, false>), grid, block, 0, st, a, c0);
+    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, false, TRACK>), grid, block, 0, st, a, c0);
 }
 
 template <class PR, int MT>
 static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
-  // forward: at most 4 waves per patch so phi_part has a slot per wave
-  constexpr int CT = (MT <= 2) ? MT : 2;
-  fwd_launch<PR, MT, CT>(a, c0, cnt, st);
+  const bool single = (cnt == 1);
+  if (single && (a.norm || a.probe_step))
+    fwd_launch<PR, MT, true>(a, c0, cnt, st);
+  else
+    fwd_launch<PR, MT, false>(a, c0, cnt, st);
   dim3 grid(cnt), block(64 * adj_waves(a.nb));
-  hipLaunchKernelGGL((k_pie_adjoint<PR, MT>), grid, block, 0, st, a, c0);
+  if (single)
+    hipLaunchKernelGGL((k_pie_adjoint<PR, MT, true>), grid, block, 0, st, a, c0);
+  else
+    hipLaunchKernelGGL((k_pie_adjoint<PR, MT, false>), grid, block, 0, st, a, c0);
 }
 
 template <int MT>
@@ -336,11 +526,7 @@ static void chunk_mt(const PieArgs& a, int c0, int cnt, hipStream_t st) {
     chunk_prec<PrecF32, MT>(a, c0, cnt, st);
 }
 
-static int ew_blocks(size_t work) {
-  size_t b = (work + 255) / 256;
-  if (b > 4096) b = 4096;
-  return b < 1 ? 1 : (int)b;
-}
+int pie_probe_blocks(int n) { return (int)(((size_t)n * n + 255) / 256); }
 
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st) {
   hipLaunchKernelGGL(k_crop_amp, dim3(ew_blocks((size_t)J * m * m)), dim3(256), 0, st, I, J, n, m, amp);
@@ -350,6 +536,8 @@ hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipS
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   const size_t obj = (size_t)a.H * a.W;
   hipLaunchKernelGGL(k_pie_begin, dim3(ew_blocks(obj)), dim3(256), 0, st, a);
+  const int ntiles = a.tiles_x * a.tiles_y;
+  const int pblocks = pie_probe_blocks(a.n);
   for (int c0 = 0; c0 < a.J; c0 += batch) {
     const int cnt = (a.J - c0 < batch) ? a.J - c0 : batch;
     switch (a.mt) {
@@ -363,17 +551,17 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
       case 8: chunk_mt<8>(a, c0, cnt, st); break;
       default: return hipErrorInvalidValue;
     }
-    if (a.mode != kModeDirect) {
-      const int single = (cnt == 1);
-      const size_t area = single ? (size_t)a.n * a.n : (size_t)a.bb_h * a.bb_w;
-      if (a.norm) {
-        hipLaunchKernelGGL(k_pie_clear_max, dim3(1), dim3(64), 0, st, a);
-        hipLaunchKernelGGL(k_pie_max, dim3(ew_blocks(area)), dim3(256), 0, st, a, c0, single);
-      }
-      hipLaunchKernelGGL(k_pie_apply, dim3(ew_blocks(area)), dim3(256), 0, st, a, c0, single);
+    if (cnt == 1) continue;  // updated in place by the adjoint
+    if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt);
+    hipLaunchKernelGGL(k_pie_object_gather, dim3(ntiles), dim3(256), 0, st, a, c0, cnt);
+    if (a.norm) hipLaunchKernelGGL(k_pie_reduce_max, dim3(1), dim3(1024), 0, st, a, a.probe_step ? pblocks : 0);
+    if (a.norm || a.probe_step) {
+      const size_t area = a.norm ? (size_t)a.bb_h * a.bb_w : (size_t)a.n * a.n;
+      hipLaunchKernelGGL(k_pie_apply, dim3(ew_blocks(area)), dim3(256), 0, st, a, a.norm);
     }
   }
-  hipLaunchKernelGGL(k_pie_stats, dim3(ew_blocks(obj)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(64), 0, st, a, kStatBlocks);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ struct PlainSrc {
 // ctiles x NB blocks.  c2t0: first column tile this wave owns.
 template <int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
-                                         f32x4 (&Yim)[MT][CT]) {
+                                         f32x4 (&Yim)[MT][CT], int strip0 = 0, int sstep = 1) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -68,7 +68,7 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
       Yre[a][b] = zero4();
       Yim[a][b] = zero4();
     }
-  for (int strip = 0; strip < NB; ++strip) {
+  for (int strip = strip0; strip < NB; strip += sstep) {
     const int row = strip * 16 + r16;
     f32x4 Tre[CT], Tim[CT];
 #pragma unroll

@@ -85,7 +85,8 @@ __device__ __forceinline__ SplitOp<PR> make_op(const float (&re)[8], const float
 // block ahead.
 template <class PR, int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab& FA, int c2t0,
-                                               f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT]) {
+                                               f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
+                                               int sstep = 1) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -95,7 +96,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
       Yre[a][b] = zero4();
       Yim[a][b] = zero4();
     }
-  for (int strip = 0; strip < NB; ++strip) {
+  for (int strip = strip0; strip < NB; strip += sstep) {
     const int row = strip * 16 + r16;
     f32x4 Tre[CT], Tim[CT];
 #pragma unroll
@@ -264,11 +265,12 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
 
 template <class PR, int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_engine(const Src& src, int NB, const Tab& FA, int c2t0,
-                                           f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT]) {
+                                           f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
+                                           int sstep = 1) {
   if constexpr (Orient<PR>::TR)
-    fwd_wave_split<PR, MT, CT>(src, NB, FA, c2t0, Yre, Yim);
+    fwd_wave_split<PR, MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
   else
-    fwd_wave<MT, CT>(src, NB, FA, c2t0, Yre, Yim);
+    fwd_wave<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
 }
 
 template <class PR, int MT, class YSrc, class Sink, class Tab>

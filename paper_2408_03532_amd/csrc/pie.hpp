@@ -19,14 +19,17 @@ struct PieArgs {
   // problem
   int n, m, nb, mt, J, H, W;
   int bb_r0, bb_c0, bb_h, bb_w;  // bounding box of all windows
+  int tiles_x, tiles_y;          // 16 x 16 pixel tiles over the bounding box
   const int2* pos;               // [J] (row, col)
   const int32_t* order;          // [J] or null
+  const int32_t* tile_ptr;       // [tiles + 1] cover lists (CSR): positions whose window meets the tile
+  const int32_t* tile_pos;
   const void* fa;
   const void* ft;
   int prec;
   float inv_n2;
   // parameters
-  int mode, norm, probe_step;
+  int norm, probe_step;
   float beta, gamma;
   double alpha;
   // data
@@ -34,19 +37,27 @@ struct PieArgs {
   float2* P;        // [n][n]
   const float* amp; // [J][m][m]
   // workspace
-  float2* R;        // [batch][m][m] residuals
+  float2* R;        // [batch][m][m] residuals u' - u
+  float2* dpsi;     // [batch][n][n] corrections (chunks of more than one position)
   double* phi_part; // [J][4]
+  int32_t* rank;    // [J] place of each position in the sweep order
+  unsigned* winmax; // [J][2] float bits of max |P|^2, max |O_j|^2 over the window (single-position chunks)
   float2* O0;       // [H][W] object at sweep start
-  float2* numO;     // [H][W] or null
-  double* D;        // [H][W] or null
-  float2* numP;     // [n][n] or null
-  double* E;        // [n][n] or null
+  float2* numO;     // [H][W] (norm 1, multi-position chunks)
+  double* D;        // [H][W]
+  float2* numP;     // [n][n] (probe step, multi-position chunks)
+  double* E;        // [n][n]
+  double* maxpart;  // [tiles + probe blocks] per-block maxima of D and E
   double* maxes;    // [2]
+  double* red;      // [kStatBlocks][3] statistics partials
   double* stats;    // [4]
 };
 
+constexpr int kStatBlocks = 512;
+
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);
+int pie_probe_blocks(int n);
 
 #ifdef __HIPCC__
 // psi[k1][k2] = P[k1][k2] * O[r + k1][c + k2]; zero outside the n x n patch.
@@ -80,5 +91,9 @@ struct pie_scan_s {
   pftpie_plan_s* plan;
   int32_t J, H, W;
   int bb_r0, bb_c0, bb_h, bb_w;
-  int2* pos;  // device [J]
+  int tiles_x, tiles_y;
+  int2* pos;           // device [J]
+  int32_t* tile_ptr;   // device [tiles + 1]
+  int32_t* tile_pos;   // device [nnz]
+  int64_t nnz;
 };

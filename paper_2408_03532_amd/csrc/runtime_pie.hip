@@ -1,4 +1,5 @@
 // C ABI of the PIE sweep: scans, workspace sizing, validation, dispatch.
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
@@ -15,12 +16,13 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace carve-up of one sweep; sizes in bytes, offsets 256-aligned.
 struct PieLayout {
-  size_t R, phi, O0, numO, D, numP, E, maxes, stats, total;
+  size_t R, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxpart, maxes, red, stats, total;
 };
 
-PieLayout pie_layout(const pie_scan_s* s, int batch, int mode, int norm, int probe_step) {
+PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
   const pftpie_plan_s* p = s->plan;
   const size_t obj = (size_t)s->H * s->W, nn = (size_t)p->n * p->n;
+  const bool multi = batch > 1;
   PieLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -29,13 +31,18 @@ PieLayout pie_layout(const pie_scan_s* s, int batch, int mode, int norm, int pro
     return o;
   };
   L.R = take((size_t)batch * p->m * p->m * 8);
+  L.dpsi = multi ? take((size_t)batch * nn * 8) : SIZE_MAX;
   L.phi = take((size_t)s->J * 4 * 8);
+  L.rank = take((size_t)s->J * 4);
+  L.winmax = take((size_t)s->J * 8);
   L.O0 = take(obj * 8);
-  L.numO = (mode == kModeAccum) ? take(obj * 8) : SIZE_MAX;
-  L.D = norm ? take(obj * 8) : SIZE_MAX;
-  L.numP = probe_step ? take(nn * 8) : SIZE_MAX;
-  L.E = (probe_step && norm) ? take(nn * 8) : SIZE_MAX;
+  L.numO = (multi && norm) ? take(obj * 8) : SIZE_MAX;
+  L.D = (multi && norm) ? take(obj * 8) : SIZE_MAX;
+  L.numP = (multi && probe_step) ? take(nn * 8) : SIZE_MAX;
+  L.E = (multi && probe_step && norm) ? take(nn * 8) : SIZE_MAX;
+  L.maxpart = take(((size_t)s->tiles_x * s->tiles_y + pie_probe_blocks(p->n)) * 8);
   L.maxes = take(16);
+  L.red = take((size_t)kStatBlocks * 3 * 8);
   L.stats = take(32);
   L.total = off;
   return L;
@@ -51,8 +58,6 @@ pftpie_status check_params(const pie_scan_s* s, const pie_params* p) {
   if (p->gamma < 0.f || p->alpha < 0.f) return fail(PFTPIE_E_INVALID, "pie: gamma and alpha must be >= 0");
   return PFTPIE_OK;
 }
-
-int mode_of(const pie_params* p) { return (p->norm == 0 && p->gamma == 0.f) ? kModeDirect : kModeAccum; }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
@@ -103,14 +108,50 @@ pftpie_status pie_scan_create(pftpie_plan plan, const int32_t* host_pos, int32_t
   s->bb_c0 = c0;
   s->bb_h = r1 - r0;
   s->bb_w = c1 - c0;
+  // cover lists: for each 16 x 16 tile of the bounding box, the positions
+  // whose window meets it (CSR, positions in increasing order)
+  s->tiles_y = (s->bb_h + 15) / 16;
+  s->tiles_x = (s->bb_w + 15) / 16;
+  const size_t ntiles = (size_t)s->tiles_x * s->tiles_y;
+  std::vector<int32_t> cnt(ntiles + 1, 0);
+  auto tile_range = [&](int32_t j, int& ty0, int& ty1, int& tx0, int& tx1) {
+    ty0 = (pos[2 * j] - r0) / 16;
+    ty1 = (pos[2 * j] + n - 1 - r0) / 16;
+    tx0 = (pos[2 * j + 1] - c0) / 16;
+    tx1 = (pos[2 * j + 1] + n - 1 - c0) / 16;
+  };
+  for (int32_t j = 0; j < J; ++j) {
+    int ty0, ty1, tx0, tx1;
+    tile_range(j, ty0, ty1, tx0, tx1);
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) ++cnt[(size_t)ty * s->tiles_x + tx + 1];
+  }
+  for (size_t t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1), lists((size_t)cnt[ntiles]);
+  for (int32_t j = 0; j < J; ++j) {
+    int ty0, ty1, tx0, tx1;
+    tile_range(j, ty0, ty1, tx0, tx1);
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) lists[(size_t)fill[(size_t)ty * s->tiles_x + tx]++] = j;
+  }
+  s->nnz = (int64_t)lists.size();
   hipError_t e = hipMalloc((void**)&s->pos, sizeof(int2) * (size_t)J);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->tile_ptr, sizeof(int32_t) * (ntiles + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&s->tile_pos, sizeof(int32_t) * std::max<size_t>(1, lists.size()));
   if (e != hipSuccess) {
+    (void)hipFree(s->pos);
+    (void)hipFree(s->tile_ptr);
     delete s;
     return fail(PFTPIE_E_NOMEM, std::string("pie_scan_create: hipMalloc: ") + hipGetErrorString(e));
   }
   e = hipMemcpy(s->pos, pos.data(), sizeof(int2) * (size_t)J, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->tile_ptr, cnt.data(), sizeof(int32_t) * (ntiles + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !lists.empty())
+    e = hipMemcpy(s->tile_pos, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(s->pos);
+    (void)hipFree(s->tile_ptr);
+    (void)hipFree(s->tile_pos);
     delete s;
     return hip_fail(e, "pie_scan_create: upload");
   }
@@ -121,6 +162,8 @@ pftpie_status pie_scan_create(pftpie_plan plan, const int32_t* host_pos, int32_t
 pftpie_status pie_scan_destroy(pie_scan scan) {
   if (!scan) return PFTPIE_OK;
   (void)hipFree(scan->pos);
+  (void)hipFree(scan->tile_ptr);
+  (void)hipFree(scan->tile_pos);
   delete scan;
   return PFTPIE_OK;
 }
@@ -129,7 +172,7 @@ pftpie_status pie_workspace_size(pie_scan scan, const pie_params* p, size_t* byt
   if (pftpie_status st = check_params(scan, p)) return st;
   if (!bytes) return fail(PFTPIE_E_INVALID, "pie_workspace_size: bytes is NULL");
   const int batch = p->batch < scan->J ? p->batch : scan->J;
-  *bytes = pie_layout(scan, batch, mode_of(p), p->norm, p->gamma > 0.f).total;
+  *bytes = pie_layout(scan, batch, p->norm, p->gamma > 0.f).total;
   return PFTPIE_OK;
 }
 
@@ -143,8 +186,8 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   if (stats_dev && (uintptr_t)stats_dev % 8) return fail(PFTPIE_E_INVALID, "pie_sweep: misaligned stats");
   const pftpie_plan_s* pl = scan->plan;
   const int batch = p->batch < scan->J ? p->batch : scan->J;
-  const int mode = mode_of(p), probe_step = p->gamma > 0.f;
-  const PieLayout L = pie_layout(scan, batch, mode, p->norm, probe_step);
+  const int probe_step = p->gamma > 0.f;
+  const PieLayout L = pie_layout(scan, batch, p->norm, probe_step);
   if (!workspace || ws_bytes < L.total)
     return fail(PFTPIE_E_INVALID, "pie_sweep: workspace smaller than pie_workspace_size (" +
                                       std::to_string(L.total) + " bytes)");
@@ -156,6 +199,7 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
       overlaps(amp, ab, workspace, L.total))
     return fail(PFTPIE_E_INVALID, "pie_sweep: object, probe, amplitudes and workspace must not overlap");
   char* ws = static_cast<char*>(workspace);
+  auto at = [&](size_t off) -> void* { return off == SIZE_MAX ? nullptr : ws + off; };
   PieArgs a{};
   a.n = pl->n;
   a.m = pl->m;
@@ -168,13 +212,16 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.bb_c0 = scan->bb_c0;
   a.bb_h = scan->bb_h;
   a.bb_w = scan->bb_w;
+  a.tiles_x = scan->tiles_x;
+  a.tiles_y = scan->tiles_y;
   a.pos = scan->pos;
   a.order = order_dev;
+  a.tile_ptr = scan->tile_ptr;
+  a.tile_pos = scan->tile_pos;
   a.fa = pl->fa;
   a.ft = pl->ft;
   a.prec = pl->prec;
   a.inv_n2 = (float)(1.0 / ((double)pl->n * pl->n));
-  a.mode = mode;
   a.norm = p->norm;
   a.probe_step = probe_step;
   a.beta = p->beta;
@@ -183,15 +230,20 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.O = static_cast<float2*>(object);
   a.P = static_cast<float2*>(probe);
   a.amp = amp;
-  a.R = reinterpret_cast<float2*>(ws + L.R);
-  a.phi_part = reinterpret_cast<double*>(ws + L.phi);
-  a.O0 = reinterpret_cast<float2*>(ws + L.O0);
-  a.numO = L.numO != SIZE_MAX ? reinterpret_cast<float2*>(ws + L.numO) : nullptr;
-  a.D = L.D != SIZE_MAX ? reinterpret_cast<double*>(ws + L.D) : nullptr;
-  a.numP = L.numP != SIZE_MAX ? reinterpret_cast<float2*>(ws + L.numP) : nullptr;
-  a.E = L.E != SIZE_MAX ? reinterpret_cast<double*>(ws + L.E) : nullptr;
-  a.maxes = reinterpret_cast<double*>(ws + L.maxes);
-  a.stats = stats_dev ? stats_dev : reinterpret_cast<double*>(ws + L.stats);
+  a.R = static_cast<float2*>(at(L.R));
+  a.dpsi = static_cast<float2*>(at(L.dpsi));
+  a.phi_part = static_cast<double*>(at(L.phi));
+  a.rank = static_cast<int32_t*>(at(L.rank));
+  a.winmax = static_cast<unsigned*>(at(L.winmax));
+  a.O0 = static_cast<float2*>(at(L.O0));
+  a.numO = static_cast<float2*>(at(L.numO));
+  a.D = static_cast<double*>(at(L.D));
+  a.numP = static_cast<float2*>(at(L.numP));
+  a.E = static_cast<double*>(at(L.E));
+  a.maxpart = static_cast<double*>(at(L.maxpart));
+  a.maxes = static_cast<double*>(at(L.maxes));
+  a.red = static_cast<double*>(at(L.red));
+  a.stats = stats_dev ? stats_dev : static_cast<double*>(at(L.stats));
   hipError_t e = launch_pie_sweep(a, batch, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pie_sweep: launch");
 }
