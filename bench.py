@@ -1,33 +1,70 @@
-"""Benchmark of the batched partial transform on one MI355X.
+"""Benchmark of the batched partial transform and the PIE sweep on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
 
-Workload: the standalone batched transform, 4096 complex64 patches of
-256 x 256 (Re/Im iid N(0,1), seeded), keeping the centred m = 64
+Headline workload: the standalone batched transform, 4096 complex64 patches
+of 256 x 256 (Re/Im iid N(0,1), seeded), keeping the centred m = 64
 frequencies per axis.  One step = pft2d_forward over the whole batch plus
-pft2d_adjoint over an independent [4096][64][64] batch (both resident in
+pft2d_adjoint over an independent [4096][64][64] batch (inputs resident in
 HBM before timing starts).  value = patches per second (one forward and one
 adjoint per patch).
 
-Prints one JSON line.  The roofline object describes the forward kernel:
-achieved = its algorithmic flops per launch (8 n m (n + m) per patch) over
-its average duration, timed with events on the stream the kernel runs on.
-The cpu_baseline leg times the FP64 oracle on a bounded sample of the same
-patches on the host cores and also reports the GPU output's relative error
-against it.
+The roofline object describes the forward kernel: achieved = its
+algorithmic flops per launch (8 n m (n + m) per patch) over its average
+duration, timed with events on the stream the kernel runs on.  The
+cpu_baseline leg times the FP64 oracle on a bounded sample of the same
+patches on the host cores and reports the GPU outputs' relative error
+against it.  The "extra" object holds the secondary measurements: the split
+precisions on the same batch, PIE iterations per second on the at-scale and
+tiny workloads, and the uneven grouped batch.
+
+Prints one JSON line.
 """
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 import numpy as np
 
 METRIC = "PFT patches/sec + PIE iters/sec at stated rel. error vs FP64 oracle"
-PEAK = {"fp32": ("mfma", 157.3, "TFLOP/s"), "split_bf16": ("hbm", 8000.0, "GB/s"),
-        "split_fp16": ("hbm", 8000.0, "GB/s")}
+PEAK_FP32 = 157.3      # TFLOP/s, dense FP32 (vector and matrix)
+PEAK_HBM = 8000.0      # GB/s
+PEAK_BF16 = 2516.6     # TFLOP/s, dense BF16 / FP16 MFMA
+
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pft2d_forward_4096x256_m64_hbm_traffic.md")
+# sources that define the forward kernel; the recorded traffic is reported
+# only while they are unchanged since the counters were taken
+FORWARD_SOURCES = ["device_common.hpp", "pft_engine.hpp", "pft_split.hpp", "kernels_pft.hip", "internal.hpp",
+                   "twiddle.cpp", "twiddle.hpp"]
+
+
+def forward_source_hash():
+    h = hashlib.sha256()
+    for f in FORWARD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2408_03532_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(prec):
+    """HBM bytes per forward launch from the committed counter summary
+    (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale), or None when the
+    summary is missing or the kernel sources changed since."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic\s+%s\s+bytes_per_launch=(\d+)\s+source=([0-9a-f]+)" % re.escape(prec), txt)
+    if not m or m.group(2) != forward_source_hash():
+        return None
+    return int(m.group(1))
 
 
 def parse():
@@ -35,11 +72,32 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=sorted(PEAK))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16", "split_fp16"])
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     return ap.parse_args()
+
+
+def ev_pair(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_calls(torch, fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` calls, events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = ev_pair(torch)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
 
 
 def make_inputs(torch, n, m, B):
@@ -52,9 +110,11 @@ def make_inputs(torch, n, m, B):
     return x, y
 
 
-def cpu_baseline(n, m, gpu_fwd, gpu_adj, seconds):
-    """FP64 oracle, timed on the host: forward + adjoint per patch, patches of
-    the same seeded batch, until ``seconds`` have elapsed."""
+def cpu_baseline(n, m, gpu_out, seconds):
+    """FP64 oracle timed on the host: forward + adjoint per patch, over
+    patches of the same seeded batch, until `seconds` have elapsed.  Also
+    returns the relative error of each GPU result given in gpu_out
+    ({name: (forward[:64], adjoint[:64])}) against the oracle."""
     import workloads
     from oracle import pft as opft
     try:
@@ -65,27 +125,79 @@ def cpu_baseline(n, m, gpu_fwd, gpu_adj, seconds):
     idx = np.arange(64)
     xs = workloads.pft_patches(n, idx)
     ys = workloads.pft_coeffs(m, idx)
+    fwd_ref = np.zeros((64, m, m), complex)
+    adj_ref = np.zeros((64, n, n), complex)
     done = 0
     t0 = time.perf_counter()
-    fwd_ref = adj_ref = None
-    while time.perf_counter() - t0 < seconds:
+    while time.perf_counter() - t0 < seconds or done < 64:
         k = done % 64
         f = opft.forward(xs[k], m)
         a = opft.adjoint(ys[k], n)
         if done < 64:
-            if fwd_ref is None:
-                fwd_ref = np.zeros((64, m, m), complex)
-                adj_ref = np.zeros((64, n, n), complex)
             fwd_ref[k], adj_ref[k] = f, a
         done += 1
     el = time.perf_counter() - t0
-    cnt = min(done, 64)
-    err_f = np.linalg.norm(gpu_fwd[:cnt] - fwd_ref[:cnt]) / np.linalg.norm(fwd_ref[:cnt])
-    err_a = np.linalg.norm(gpu_adj[:cnt] - adj_ref[:cnt]) / np.linalg.norm(adj_ref[:cnt])
+    errs = {}
+    for name, (gf, ga) in gpu_out.items():
+        errs[name] = {"forward": float(np.linalg.norm(gf - fwd_ref) / np.linalg.norm(fwd_ref)),
+                      "adjoint": float(np.linalg.norm(ga - adj_ref) / np.linalg.norm(adj_ref)),
+                      "patches_checked": 64}
     return ({"value": done / el, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
-             "sample": f"{done} patch forward+adjoint pairs (n={n}, m={m}) from the first 64 "
-                       f"patches of the batch, {el:.1f} s, numpy complex128"},
-            {"forward": float(err_f), "adjoint": float(err_a), "patches_checked": int(cnt)})
+             "sample": f"{done} forward+adjoint patch pairs (n={n}, m={m}, the first 64 patches of the "
+                       f"batch, cycled) in {el:.1f} s, numpy complex128"}, errs)
+
+
+def pie_at_scale_rate(torch, pk, precision, sweeps=10, warmup=2):
+    """Phase-1 sweeps of the warm-started workload (1024^2 object, 128^2
+    probe, 900 positions, m = 32, fully batched, overlap-normalised)."""
+    import workloads
+    case = workloads.pie_at_scale()
+    scan = pk.Scan(case["pos"], (1024, 1024), 128, 32, precision=precision)
+    I = torch.from_numpy(case["intensity"]).cuda()
+    amp = pk.crop_amplitudes(I, 32)
+    O = torch.from_numpy(case["init"]).cuda()
+    P = torch.from_numpy(case["probe"]).cuda()
+    prm = pk.PieParams(batch=900, norm=1, beta=1.0, alpha=1e-3)
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ms = time_calls(torch, lambda: pk.pie_sweep(O, P, scan, amp, prm, stats=stats), sweeps, warmup)
+    return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "positions": 900, "n": 128, "m": 32,
+            "precision": precision, "phi_last": float(stats[0].item())}
+
+
+def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
+    import workloads
+    case = workloads.tiny_pie()
+    scan = pk.Scan(case["pos"], (128, 128), 32, 16)
+    amp = torch.from_numpy(case["amp"]).cuda()
+    O = torch.from_numpy(case["init"]).cuda()
+    P = torch.from_numpy(case["probe"]).cuda()
+    prm = pk.PieParams(batch=batch, norm=norm, beta=1.0, alpha=1e-3)
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ms = time_calls(torch, lambda: pk.pie_sweep(O, P, scan, amp, prm, stats=stats), sweeps, warmup)
+    return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "batch": batch, "norm": norm}
+
+
+def group_rate(torch, pk, precisions, steps=5, warmup=2):
+    """Uneven batch: 8192 descriptors, n in {64,128,256,512}, m = n/4, one
+    persistent launch per call (graph replay).  Inputs drawn on the device
+    (seeded); correctness of this path is covered by the parity tests."""
+    import workloads
+    d, tin, tout = workloads.grouped_descs()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = torch.randn(tin, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty(tout, dtype=torch.complex64, device="cuda")
+    flops = float(np.sum(8.0 * d[:, 0] * d[:, 1] * (d[:, 0] + d[:, 1])))
+    byts = float((tin + tout) * 8)
+    out = {}
+    for p in precisions:
+        grp = pk.Group(d, tin, tout, p)
+        ms = time_calls(torch, lambda: grp.run(x, y), steps, warmup)
+        out[p] = {"forward_ms": ms, "patches_per_s": len(d) / ms * 1e3, "tflops_alg": flops / ms / 1e9,
+                  "gbs_alg": byts / ms / 1e6}
+        grp.close()
+    del x, y
+    return out
 
 
 def main():
@@ -109,7 +221,6 @@ def main():
         plan.forward(x, yout)
         plan.adjoint(yin, xout)
     torch.cuda.synchronize()
-
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -124,14 +235,17 @@ def main():
     el = time.perf_counter() - t0
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
     adj_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    gpu_out = {prec: (yout[:64].cpu().numpy(), xout[:64].cpu().numpy())}
 
     flops = 8.0 * n * m * (n + m) * B
-    bytes_ = (n * n + m * m) * 8.0 * B
-    bound, peak, unit = PEAK[prec]
-    if bound == "mfma":
-        achieved = flops / (fwd_ms * 1e-3) / 1e12
+    bytes_fwd = (n * n + m * m) * 8.0 * B
+    if prec == "fp32":
+        roof = {"bound": "mfma", "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": PEAK_FP32,
+                "unit": "TFLOP/s"}
     else:
-        achieved = bytes_ / (fwd_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": bytes_fwd / (fwd_ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": recorded_traffic(prec), "kernel": "pft2d_forward",
+                 "alg_flops_per_launch": flops, "alg_bytes_per_launch": bytes_fwd, "kernel_ms": fwd_ms})
     out = {
         "metric": METRIC,
         "value": B * args.steps / el,
@@ -148,16 +262,43 @@ def main():
         "config": {"workload": f"standalone batched partial DFT forward+adjoint, {B} complex64 patches "
                                f"{n}x{n}, centred m={m} window, {prec}",
                    "batch": B, "n": n, "m": m, "precision": prec},
-        "kernels_ms": {"forward": fwd_ms, "adjoint": adj_ms},
-        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "pft2d_forward", "alg_flops_per_launch": flops,
-                     "alg_bytes_per_launch": bytes_},
+        "forward_source": forward_source_hash(),
+        "kernels_ms": {"forward": fwd_ms, "adjoint": adj_ms,
+                       "adjoint_tflops_alg": flops / (adj_ms * 1e-3) / 1e12},
+        "roofline": roof,
     }
+
+    if not args.no_extra:
+        extra = {}
+        for p in ("fp32", "split_bf16", "split_fp16"):
+            if p == prec:
+                continue
+            pl = pk.get_plan(n, m, p)
+            f = time_calls(torch, lambda: pl.forward(x, yout), 10, 2)
+            a = time_calls(torch, lambda: pl.adjoint(yin, xout), 10, 2)
+            extra[f"pft_{p}"] = {"forward_ms": f, "adjoint_ms": a, "patches_per_s": B / (f + a) * 1e3,
+                                 "forward_hbm_frac": bytes_fwd / (f * 1e-3) / 1e9 / PEAK_HBM,
+                                 "forward_tflops_alg": flops / (f * 1e-3) / 1e12}
+            gpu_out[p] = (yout[:64].cpu().numpy(), xout[:64].cpu().numpy())
+        del x, xout
+        torch.cuda.empty_cache()
+        extra["pie_at_scale_phase1"] = pie_at_scale_rate(torch, pk, "fp32")
+        extra["pie_at_scale_phase1_split_bf16"] = pie_at_scale_rate(torch, pk, "split_bf16")
+        extra["pie_tiny_sequential"] = pie_tiny_rate(torch, pk, 1, 0)
+        extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
+        extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])
+        out["extra"] = extra
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * src.numel() * 8
+
     if not args.no_cpu:
-        g_f = yout[:64].cpu().numpy()
-        g_a = xout[:64].cpu().numpy()
-        out["cpu_baseline"], out["rel_err_vs_oracle"] = cpu_baseline(n, m, g_f, g_a, args.cpu_seconds)
+        out["cpu_baseline"], out["rel_err_vs_oracle"] = cpu_baseline(n, m, gpu_out, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
