@@ -177,6 +177,25 @@ def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
     return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "batch": batch, "norm": norm}
 
 
+def loss_rate(torch, pk, precision="fp32", steps=5, warmup=1):
+    """Amplitude loss and gradient: 1024 positions, 256^2 patches, m = 64 on
+    a 2304^2 object (forward with stored spectra, backward from them, and
+    backward recomputing them)."""
+    import workloads
+    case = workloads.amp_loss_case()
+    O = torch.from_numpy(case["obj"]).cuda()
+    P = torch.from_numpy(case["probe"]).cuda()
+    A = torch.from_numpy(case["amp"]).cuda()
+    scan = pk.Scan(case["pos"], O.shape, 256, 64, precision=precision)
+    u = torch.empty(1024, 64, 64, dtype=torch.complex64, device="cuda")
+    f = time_calls(torch, lambda: pk.amp_loss(O, P, scan, A, saved_u=u), steps, warmup)
+    b = time_calls(torch, lambda: pk.amp_loss_grad(O, P, scan, A, saved_u=u), steps, warmup)
+    br = time_calls(torch, lambda: pk.amp_loss_grad(O, P, scan, A), steps, warmup)
+    flops = 8.0 * 256 * 64 * 320 * 1024
+    return {"forward_ms": f, "backward_ms": b, "backward_recompute_ms": br,
+            "fwd_bwd_tflops_alg": 2 * flops / ((f + b) * 1e-3) / 1e12, "precision": precision}
+
+
 def group_rate(torch, pk, precisions, steps=5, warmup=2):
     """Uneven batch: 8192 descriptors, n in {64,128,256,512}, m = n/4, one
     persistent launch per call (graph replay).  Inputs drawn on the device
@@ -287,6 +306,7 @@ def main():
         extra["pie_tiny_sequential"] = pie_tiny_rate(torch, pk, 1, 0)
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])
+        extra["amp_loss_1024x256"] = loss_rate(torch, pk)
         out["extra"] = extra
 
     if args.copy_calibration:

@@ -203,8 +203,10 @@ pftpie_status pie_crop_amplitudes(const float* intensity, int32_t J, int32_t n, 
  *   scale * dL/dP) or NULL, where scale = *grad_scale_dev (device double) or
  *   1 when grad_scale_dev is NULL.  saved_u: the u_j written by
  *   amp_loss_forward, or NULL to recompute them (one more forward
- *   transform).  The exit waves themselves are never stored.  workspace as
- *   sized by amp_loss_workspace_size (256-byte aligned). */
+ *   transform).  The exit waves themselves are never stored; the workspace
+ *   (amp_loss_workspace_size, 256-byte aligned) holds the back-projected
+ *   residuals R_j [J][n][n] that the object and probe gradients are gathered
+ *   from (no atomics, deterministic summation order). */
 pftpie_status amp_loss_workspace_size(pie_scan scan, size_t* bytes);
 pftpie_status amp_loss_forward(pie_scan scan, const void* object, const void* probe,
                                const float* amp, double* loss_dev, void* saved_u,

@@ -7,8 +7,11 @@
 // k_loss_forward   gathers psi_j in its operand loader, transforms, writes
 //                  u_j (optional) and per-wave partial losses.
 // k_loss_adjoint   forms G_j from u_j and a_j in its operand loader, applies
-//                  the adjoint and scatters both gradients in its epilogue;
-//                  the exit waves are never stored.
+//                  the adjoint and stores scale * R_j; the exit waves are
+//                  never stored.
+// k_loss_object_gather  per 16 x 16 object tile, sums conj(P) R_j over the
+//                  positions of the tile's cover list (no atomics).
+// k_loss_probe_gather   per probe pixel, sums conj(O_j) R_j over positions.
 #include "internal.hpp"
 #include "loss.hpp"
 #include "pft_split.hpp"
@@ -73,12 +76,9 @@ struct GradSrc {
   }
 };
 
-struct GradSink {
-  const float2* __restrict__ O;
-  const float2* __restrict__ P;
-  float2* __restrict__ gO;
-  float2* __restrict__ gP;
-  int n, W, r, c;
+struct RSink {
+  float2* __restrict__ out;
+  int n;
   float scale;
   template <bool TR>
   __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
@@ -86,20 +86,7 @@ struct GradSink {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int2 rc = tile_rc<TR>(k1t, k2t, i, lane);
-      const int k1 = rc.x, k2 = rc.y;
-      if (k1 < n && k2 < n) {
-        const float2 R = make_float2(scale * xre[i], scale * xim[i]);
-        const size_t pi = (size_t)k1 * n + k2;
-        const size_t o = (size_t)(r + k1) * W + (c + k2);
-        const float2 vo = cmulc(P[pi], R);  // conj(P) R
-        unsafeAtomicAdd(&gO[o].x, vo.x);
-        unsafeAtomicAdd(&gO[o].y, vo.y);
-        if (gP) {
-          const float2 vp = cmulc(O[o], R);  // conj(O_j) R
-          unsafeAtomicAdd(&gP[pi].x, vp.x);
-          unsafeAtomicAdd(&gP[pi].y, vp.y);
-        }
-      }
+      if (rc.x < n && rc.y < n) out[(size_t)rc.x * n + rc.y] = make_float2(scale * xre[i], scale * xim[i]);
     }
   }
 };
@@ -108,12 +95,70 @@ template <class PR, int MT>
 __global__ __launch_bounds__(256) void k_loss_adjoint(LossArgs a) {
   const int j = blockIdx.x;
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int2 ps = a.pos[j];
   const size_t mm = (size_t)a.m * a.m;
   GradSrc src{a.Uc + (size_t)j * mm, a.amp + (size_t)j * mm, a.m};
   const float scale = a.scale_dev ? (float)a.scale_dev[0] : 1.f;
-  GradSink sink{a.O, a.P, a.gO, a.gP, a.n, a.W, ps.x, ps.y, scale};
-  for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, TabG{static_cast<const char*>(a.ft)}, kt2, sink);
+  RSink sink{a.Rbuf + (size_t)j * a.n * a.n, a.n, scale};
+  for (int kt2 = w; kt2 < a.nb; kt2 += nw)
+    adj_engine<PR, MT>(src, a.nb, TabG{static_cast<const char*>(a.ft)}, kt2, sink);
+}
+
+// dL/dO over the bounding box: per 16 x 16 tile, every position of its cover
+// list whose window holds the pixel contributes conj(P) R_j.
+__global__ __launch_bounds__(256) void k_loss_object_gather(LossArgs a) {
+  const int tile = blockIdx.x;
+  const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
+  const int py = a.bb_r0 + ty * 16 + (threadIdx.x >> 4);
+  const int px = a.bb_c0 + tx * 16 + (threadIdx.x & 15);
+  if (py >= a.bb_r0 + a.bb_h || px >= a.bb_c0 + a.bb_w) return;
+  const size_t nn = (size_t)a.n * a.n;
+  float2 acc = make_float2(0.f, 0.f);
+  const int e0 = a.tile_ptr[tile], e1 = a.tile_ptr[tile + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = a.tile_pos[e];
+    const int2 ps = a.pos[j];
+    const int dy = py - ps.x, dx = px - ps.y;
+    if (dy < 0 || dy >= a.n || dx < 0 || dx >= a.n) continue;
+    const size_t k = (size_t)dy * a.n + dx;
+    const float2 v = cmulc(a.P[k], a.Rbuf[(size_t)j * nn + k]);
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  a.gO[(size_t)py * a.W + px] = acc;
+}
+
+// dL/dP: per probe pixel, partial sums of conj(O_j) R_j over chunks of
+// kLossChunk positions (blockIdx.y), then a fixed-order sum of the partials.
+constexpr int kLossChunk = 64;
+
+__global__ __launch_bounds__(256) void k_loss_probe_gather(LossArgs a) {
+  const size_t nn = (size_t)a.n * a.n;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int k1 = (int)(k / a.n), k2 = (int)(k % a.n);
+  const int j0 = blockIdx.y * kLossChunk;
+  const int j1 = (j0 + kLossChunk < a.J) ? j0 + kLossChunk : a.J;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int j = j0; j < j1; ++j) {
+    const int2 ps = a.pos[j];
+    const float2 v = cmulc(a.O[(size_t)(ps.x + k1) * a.W + ps.y + k2], a.Rbuf[(size_t)j * nn + k]);
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  a.gPpart[(size_t)blockIdx.y * nn + k] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_loss_probe_sum(LossArgs a, int nchunks) {
+  const size_t nn = (size_t)a.n * a.n;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int c = 0; c < nchunks; ++c) {
+    const float2 v = a.gPpart[(size_t)c * nn + k];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  a.gP[k] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_loss_reduce(LossArgs a) {
@@ -125,19 +170,13 @@ __global__ __launch_bounds__(256) void k_loss_reduce(LossArgs a) {
   if (threadIdx.x == 0) a.loss[0] = s;
 }
 
+// dL/dO is zero outside the bounding box of the windows.
 __global__ __launch_bounds__(256) void k_loss_clear(LossArgs a) {
   const size_t total = (size_t)a.H * a.W;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x)
-    a.gO[t] = make_float2(0.f, 0.f);
-  if (a.gP) {
-    const size_t nn = (size_t)a.n * a.n;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < nn; t += (size_t)gridDim.x * blockDim.x)
-      a.gP[t] = make_float2(0.f, 0.f);
-  }
-  if (a.part) {
-    const size_t np = (size_t)a.J * 4;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < np; t += (size_t)gridDim.x * blockDim.x)
-      a.part[t] = 0.0;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / a.W), c = (int)(t % a.W);
+    if (r < a.bb_r0 || r >= a.bb_r0 + a.bb_h || c < a.bb_c0 || c >= a.bb_c0 + a.bb_w)
+      a.gO[t] = make_float2(0.f, 0.f);
   }
 }
 
@@ -220,6 +259,13 @@ hipError_t launch_loss_backward(const LossArgs& a, bool recompute, hipStream_t s
     case 7: adj_mt<7>(a, st); break;
     case 8: adj_mt<8>(a, st); break;
     default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_loss_object_gather, dim3(a.tiles_x * a.tiles_y), dim3(256), 0, st, a);
+  if (a.gP) {
+    const unsigned pb = (unsigned)(((size_t)a.n * a.n + 255) / 256);
+    const int nch = (a.J + kLossChunk - 1) / kLossChunk;
+    hipLaunchKernelGGL(k_loss_probe_gather, dim3(pb, nch), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_loss_probe_sum, dim3(pb), dim3(256), 0, st, a, nch);
   }
   return hipGetLastError();
 }

@@ -21,6 +21,11 @@ struct LossArgs {
   const double* scale_dev;
   float2* gO;
   float2* gP;
+  float2* Rbuf;           // [J][n][n] back-projected residuals (backward)
+  float2* gPpart;         // [ceil(J / 64)][n][n] partial probe gradients
+  int bb_r0, bb_c0, bb_h, bb_w, tiles_x, tiles_y;
+  const int32_t* tile_ptr;
+  const int32_t* tile_pos;
 };
 
 hipError_t launch_loss_forward(const LossArgs& a, hipStream_t st);

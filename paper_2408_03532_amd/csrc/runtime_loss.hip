@@ -9,15 +9,19 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Workspace: spectra u_j (when the backward recomputes them), per-wave loss
+// partials, back-projected residuals R_j [J][n][n] for the gradient gathers.
 struct LossLayout {
-  size_t U, part, total;
+  size_t U, part, R, Pp, total;
 };
 
 LossLayout loss_layout(const pie_scan_s* s) {
   LossLayout L;
   L.U = 0;
   L.part = al256((size_t)s->J * s->plan->m * s->plan->m * 8);
-  L.total = L.part + al256((size_t)s->J * 4 * 8);
+  L.R = L.part + al256((size_t)s->J * 4 * 8);
+  L.Pp = L.R + al256((size_t)s->J * s->plan->n * s->plan->n * 8);
+  L.total = L.Pp + al256((size_t)((s->J + 63) / 64) * s->plan->n * s->plan->n * 8);
   return L;
 }
 
@@ -61,6 +65,16 @@ LossArgs base_args(const pie_scan_s* s, const void* O, const void* P, const floa
   a.P = static_cast<const float2*>(P);
   a.amp = amp;
   a.part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part);
+  a.Rbuf = reinterpret_cast<float2*>(static_cast<char*>(ws) + L.R);
+  a.gPpart = reinterpret_cast<float2*>(static_cast<char*>(ws) + L.Pp);
+  a.bb_r0 = s->bb_r0;
+  a.bb_c0 = s->bb_c0;
+  a.bb_h = s->bb_h;
+  a.bb_w = s->bb_w;
+  a.tiles_x = s->tiles_x;
+  a.tiles_y = s->tiles_y;
+  a.tile_ptr = s->tile_ptr;
+  a.tile_pos = s->tile_pos;
   return a;
 }
 
