@@ -77,9 +77,20 @@ namespace pftpie {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// pk(a, b): RNE(a) in the low half, RNE(b) in the high half of one dword;
+// lo / hi: the float value of the low / high half.
 struct PrecBF16 {
   typedef __bf16 T;
   typedef bf16x8 V;
+  static __device__ __forceinline__ uint32_t pk(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v){a, b}, bf16x2));
+  }
+  static __device__ __forceinline__ float lo(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
+  static __device__ __forceinline__ float hi(uint32_t p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
   static __device__ __forceinline__ f32x4 mfma(V a, V b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -87,6 +98,11 @@ struct PrecBF16 {
 struct PrecF16 {
   typedef _Float16 T;
   typedef f16x8 V;
+  static __device__ __forceinline__ uint32_t pk(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v){a, b}, f16x2));
+  }
+  static __device__ __forceinline__ float lo(uint32_t p) { return (float)__builtin_bit_cast(f16x2, p).x; }
+  static __device__ __forceinline__ float hi(uint32_t p) { return (float)__builtin_bit_cast(f16x2, p).y; }
   static __device__ __forceinline__ f32x4 mfma(V a, V b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }

@@ -20,6 +20,9 @@ constexpr size_t kMaxLdsTable = 160 * 1024;  // LDS per compute unit on gfx950
 // owns CT column tiles, W = ceil(MT / CT) waves per patch.  Valid CT: 1, 2
 // (MT >= 2), 3 (MT == 3), 4 (MT == 4).
 inline int fwd_ct_default(int mt) { return mt <= 2 ? mt : 2; }
+// split precisions: all four column tiles in one wave when m <= 64 (the
+// operand split is shared by twice the products)
+inline int fwd_ct_default_split(int mt) { return mt == 4 ? 4 : fwd_ct_default(mt); }
 inline bool fwd_ct_valid(int mt, int ct) {
   return ct == 1 || (ct == 2 && mt >= 2) || (ct == 3 && mt == 3) || (ct == 4 && mt == 4);
 }
@@ -38,6 +41,8 @@ struct pftpie_plan_s {
   int fwd_ct;        // forward column tiles per wave
   int use_lds;       // persistent LDS-table kernel for the plain forward
   int use_lds_adj;   // persistent LDS-table kernel for the plain adjoint
+  int adj_k1;        // FP32 adjoint: row tiles per stage-2 step (2 or 4)
+  int adj_threads;   // FP32 persistent adjoint: threads per workgroup (512 or 768)
   int num_cu;        // compute units of the plan's device
   int device;
   void* fa;          // device FA table (float4 blocks, or split 16-bit blocks)

@@ -16,7 +16,7 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_forward(
   const int c2t0 = w * CT;
   PlainSrc<EXACT> src{psi + b * (int64_t)n * n, n};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, nb, TabG{static_cast<const char*>(fa)}, c2t0, Yre, Yim);
+  fwd_engine<PR, MT, CT>(src, nb, TabG{static_cast<const char*>(fa)}, c2t0, Yre, Yim, 0, 1, (int)(b % nb));
   const int lane = lane_id();
   float2* out = y + b * (int64_t)m * m;
 #pragma unroll
@@ -30,6 +30,23 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_forward(
       }
     }
 }
+
+// Y source of the plain adjoint, m % 16 == 0 and 16-byte aligned: two
+// 16-byte loads per chunk, every chunk in bounds.
+struct CoefSrcExact {
+  const float2* __restrict__ p;
+  int m;
+  __device__ __forceinline__ c4 load(int row, int col0) const {
+    const float4* q = reinterpret_cast<const float4*>(p + (size_t)row * m + col0);
+    const float4 a = q[0], b = q[1];
+    c4 r;
+    r.v[0] = make_float2(a.x, a.y);
+    r.v[1] = make_float2(a.z, a.w);
+    r.v[2] = make_float2(b.x, b.y);
+    r.v[3] = make_float2(b.z, b.w);
+    return r;
+  }
+};
 
 // Y source of the plain adjoint (m x m blocks, masked).
 struct CoefSrc {
@@ -82,8 +99,8 @@ __device__ __forceinline__ void copy_table_to_lds(f32x4* smem, const f32x4* __re
   __syncthreads();
 }
 
-template <class PR, int MT, int CT>
-__global__ __launch_bounds__(kLdsThreads) void k_forward_lds(const float2* __restrict__ psi, float2* __restrict__ y,
+template <class PR, int MT, int CT, int THREADS = kLdsThreads>
+__global__ __launch_bounds__(THREADS) void k_forward_lds(const float2* __restrict__ psi, float2* __restrict__ y,
                                                              int n, int m, int nb, const f32x4* __restrict__ tab,
                                                              int tab16, int64_t batch) {
   extern __shared__ f32x4 smem[];
@@ -98,7 +115,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_forward_lds(const float2* __res
     const int c2t0 = (int)(it % W) * CT;
     PlainSrc<true> src{psi + b * (int64_t)n * n, n};
     f32x4 Yre[MT][CT], Yim[MT][CT];
-    fwd_engine<PR, MT, CT>(src, nb, T, c2t0, Yre, Yim);
+    fwd_engine<PR, MT, CT>(src, nb, T, c2t0, Yre, Yim, 0, 1, (int)(b % nb));
     float2* out = y + b * (int64_t)m * m;
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t)
@@ -112,8 +129,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_forward_lds(const float2* __res
   }
 }
 
-template <class PR, int MT>
-__global__ __launch_bounds__(kLdsThreads) void k_adjoint_lds(const float2* __restrict__ y, float2* __restrict__ psi,
+template <class PR, int MT, bool EXACT, int K1, int THREADS = kLdsThreads>
+__global__ __launch_bounds__(THREADS) void k_adjoint_lds(const float2* __restrict__ y, float2* __restrict__ psi,
                                                              int n, int m, int nb, const f32x4* __restrict__ tab,
                                                              int tab16, int64_t batch) {
   extern __shared__ f32x4 smem[];
@@ -124,23 +141,29 @@ __global__ __launch_bounds__(kLdsThreads) void k_adjoint_lds(const float2* __res
   for (int64_t it = (int64_t)blockIdx.x * nwaves + wave; it < items; it += (int64_t)gridDim.x * nwaves) {
     const int64_t b = it / nb;
     const int kt2 = (int)(it % nb);
-    CoefSrc src{y + b * (int64_t)m * m, m};
     StoreSink sink{psi + b * (int64_t)n * n, n};
-    adj_engine<PR, MT>(src, nb, T, kt2, sink);
+    if constexpr (EXACT) {
+      CoefSrcExact src{y + b * (int64_t)m * m, m};
+      adj_engine<PR, MT, CoefSrcExact, StoreSink, TabL, K1>(src, nb, T, kt2, sink);
+    } else {
+      CoefSrc src{y + b * (int64_t)m * m, m};
+      adj_engine<PR, MT, CoefSrc, StoreSink, TabL, K1>(src, nb, T, kt2, sink);
+    }
   }
 }
 
 template <class K>
 static hipError_t launch_lds(K kernel, const pftpie_plan_s* p, size_t tab_bytes, int64_t items, hipStream_t st,
-                             const float2* in, float2* out, const void* tab, int64_t batch) {
+                             const float2* in, float2* out, const void* tab, int64_t batch,
+                             int threads = kLdsThreads) {
   // every instantiation is allowed the table's dynamic LDS once
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)tab_bytes);
   if (e != hipSuccess) return e;
-  const int64_t waves = kLdsThreads / 64;
+  const int64_t waves = threads / 64;
   int64_t grid = (items + waves - 1) / waves;
   if (grid > p->num_cu) grid = p->num_cu;
-  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kLdsThreads), tab_bytes, st, in, out, p->n, p->m, p->nb,
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), tab_bytes, st, in, out, p->n, p->m, p->nb,
                      static_cast<const f32x4*>(tab), (int)(tab_bytes / 16), batch);
   return hipGetLastError();
 }
@@ -149,9 +172,14 @@ template <class PR, int MT, int CT>
 static hipError_t fwd_mt_ct(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
   constexpr int W = (MT + CT - 1) / CT;
   const bool exact = (p->n % 16 == 0) && ((uintptr_t)psi % 16 == 0);
-  // (CT = 4 needs more than the 256 registers a 512-thread workgroup leaves)
-  if (exact && p->use_lds && CT <= 2 && p->fa_bytes <= kMaxLdsTable)
-    return launch_lds(k_forward_lds<PR, MT, CT>, p, p->fa_bytes, batch * W, st, psi, y, p->fa, batch);
+  // CT = 4 needs more than the 256 registers a 512-thread workgroup leaves:
+  // it runs in 256-thread workgroups (one wave per SIMD, 512 registers)
+  if (exact && p->use_lds && p->fa_bytes <= kMaxLdsTable) {
+    if constexpr (CT == 4)
+      return launch_lds(k_forward_lds<PR, MT, CT, 256>, p, p->fa_bytes, batch * W, st, psi, y, p->fa, batch, 256);
+    else
+      return launch_lds(k_forward_lds<PR, MT, CT>, p, p->fa_bytes, batch * W, st, psi, y, p->fa, batch);
+  }
   dim3 grid((unsigned)batch), block(64 * W);
   if (exact)
     hipLaunchKernelGGL((k_forward<PR, MT, CT, true>), grid, block, 0, st, psi, y, p->n, p->m, p->nb, p->fa);
@@ -162,8 +190,17 @@ static hipError_t fwd_mt_ct(const pftpie_plan_s* p, const float2* psi, float2* y
 
 template <int MT>
 static hipError_t fwd_mt(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch, hipStream_t st) {
-  if (p->prec == PFTPIE_SPLIT_BF16) return fwd_mt_ct<PrecBF16, MT, (MT < 2 ? MT : 2)>(p, psi, y, batch, st);
-  if (p->prec == PFTPIE_SPLIT_FP16) return fwd_mt_ct<PrecF16, MT, (MT < 2 ? MT : 2)>(p, psi, y, batch, st);
+  if (p->prec != PFTPIE_FP32) {
+    // split: one wave takes all four column tiles when the plan asks for it
+    // (the operand split is shared by twice the products)
+    if constexpr (MT == 4) {
+      if (p->fwd_ct == 4)
+        return p->prec == PFTPIE_SPLIT_BF16 ? fwd_mt_ct<PrecBF16, 4, 4>(p, psi, y, batch, st)
+                                           : fwd_mt_ct<PrecF16, 4, 4>(p, psi, y, batch, st);
+    }
+    return p->prec == PFTPIE_SPLIT_BF16 ? fwd_mt_ct<PrecBF16, MT, (MT < 2 ? MT : 2)>(p, psi, y, batch, st)
+                                       : fwd_mt_ct<PrecF16, MT, (MT < 2 ? MT : 2)>(p, psi, y, batch, st);
+  }
   // FP32: column tiles per wave from the plan (4 only while the Y
   // accumulators stay within 128 registers)
   switch (p->fwd_ct) {
@@ -194,11 +231,29 @@ template <int MT>
 static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch, hipStream_t st) {
   if (p->use_lds_adj && p->ft_bytes <= kMaxLdsTable) {
     const int64_t items = batch * p->nb;
+    const bool exact = (p->m % 16 == 0) && ((uintptr_t)y % 16 == 0);
     if (p->prec == PFTPIE_SPLIT_BF16)
-      return launch_lds(k_adjoint_lds<PrecBF16, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+      return exact ? launch_lds(k_adjoint_lds<PrecBF16, MT, true, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch)
+                   : launch_lds(k_adjoint_lds<PrecBF16, MT, false, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
     if (p->prec == PFTPIE_SPLIT_FP16)
-      return launch_lds(k_adjoint_lds<PrecF16, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
-    return launch_lds(k_adjoint_lds<PrecF32, MT>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+      return exact ? launch_lds(k_adjoint_lds<PrecF16, MT, true, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch)
+                   : launch_lds(k_adjoint_lds<PrecF16, MT, false, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+    if (p->adj_threads == 768) {
+      if (p->adj_k1 == 4)
+        return exact ? launch_lds(k_adjoint_lds<PrecF32, MT, true, 4, 768>, p, p->ft_bytes, items, st, y, psi, p->ft,
+                                  batch, 768)
+                     : launch_lds(k_adjoint_lds<PrecF32, MT, false, 4, 768>, p, p->ft_bytes, items, st, y, psi,
+                                  p->ft, batch, 768);
+      return exact ? launch_lds(k_adjoint_lds<PrecF32, MT, true, 2, 768>, p, p->ft_bytes, items, st, y, psi, p->ft,
+                                batch, 768)
+                   : launch_lds(k_adjoint_lds<PrecF32, MT, false, 2, 768>, p, p->ft_bytes, items, st, y, psi, p->ft,
+                                batch, 768);
+    }
+    if (p->adj_k1 == 4)
+      return exact ? launch_lds(k_adjoint_lds<PrecF32, MT, true, 4>, p, p->ft_bytes, items, st, y, psi, p->ft, batch)
+                   : launch_lds(k_adjoint_lds<PrecF32, MT, false, 4>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
+    return exact ? launch_lds(k_adjoint_lds<PrecF32, MT, true, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch)
+                 : launch_lds(k_adjoint_lds<PrecF32, MT, false, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);
   }
   dim3 grid((unsigned)batch), block(64 * adj_waves(p->nb));
   if (p->prec == PFTPIE_SPLIT_BF16)

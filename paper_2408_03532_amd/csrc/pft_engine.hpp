@@ -136,7 +136,7 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
 // Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
 // returns Y[row][col0..col0+3] (zeros outside m x m).  FT holds NB x MT
 // blocks.  sink.put<false>(k1t, kt2, Xre, Xim) receives each finished tile.
-template <int MT, class YSrc, class Sink, class Tab>
+template <int MT, class YSrc, class Sink, class Tab, int K1 = 2>
 __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Tab& FT, int kt2, Sink& sink) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
@@ -185,44 +185,53 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Ta
       stage1(f, y);
     }
   }
-  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], two row tiles at a
+  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], K1 row tiles at a
   // time; the twiddle blocks of the next step are fetched while the current
   // step's products issue (ping-pong buffers, no register copies).
-  auto fetch2 = [&](int k1t, int c1t, c4& fa, c4& fb) {
-    const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
-    fa = FT.f32((size_t)k1t * MT + c1t, lane);
-    fb = FT.f32((size_t)k1b * MT + c1t, lane);
+  auto fetch2 = [&](int k1t, int c1t, c4(&f)[K1]) {
+#pragma unroll
+    for (int u = 0; u < K1; ++u) {
+      const int kt = (k1t + u < NB) ? k1t + u : NB - 1;
+      f[u] = FT.f32((size_t)kt * MT + c1t, lane);
+    }
   };
-  c4 fa[2], fb[2];
-  fetch2(0, 0, fa[0], fb[0]);
-  for (int k1t = 0; k1t < NB; k1t += 2) {
-    const bool two = (k1t + 1 < NB);
-    const int k1n = (k1t + 2 < NB) ? k1t + 2 : k1t;
-    f32x4 Xre0 = zero4(), Xim0 = zero4(), Xre1 = zero4(), Xim1 = zero4();
+  c4 fb[2][K1];
+  fetch2(0, 0, fb[0]);
+  for (int k1t = 0; k1t < NB; k1t += K1) {
+    const int k1n = (k1t + K1 < NB) ? k1t + K1 : k1t;
+    f32x4 Xre[K1], Xim[K1];
+#pragma unroll
+    for (int u = 0; u < K1; ++u) {
+      Xre[u] = zero4();
+      Xim[u] = zero4();
+    }
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
       const int cur = c1t & 1;
       if (c1t + 1 < MT)
-        fetch2(k1t, c1t + 1, fa[cur ^ 1], fb[cur ^ 1]);
+        fetch2(k1t, c1t + 1, fb[cur ^ 1]);
       else if ((MT & 1) == 0)
-        fetch2(k1n, 0, fa[cur ^ 1], fb[cur ^ 1]);  // cur ^ 1 == 0 here
+        fetch2(k1n, 0, fb[cur ^ 1]);  // cur ^ 1 == 0 here
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float sr = Sre[c1t][i], si = Sim[c1t][i];
-        Xre0 = mfma4(fa[cur].v[i].x, sr, Xre0);
-        Xim0 = mfma4(fa[cur].v[i].x, si, Xim0);
-        Xre1 = mfma4(fb[cur].v[i].x, sr, Xre1);
-        Xim1 = mfma4(fb[cur].v[i].x, si, Xim1);
-        Xre0 = mfma4(fa[cur].v[i].y, si, Xre0);
-        Xim0 = mfma4(-fa[cur].v[i].y, sr, Xim0);
-        Xre1 = mfma4(fb[cur].v[i].y, si, Xre1);
-        Xim1 = mfma4(-fb[cur].v[i].y, sr, Xim1);
+#pragma unroll
+        for (int u = 0; u < K1; ++u) {
+          Xre[u] = mfma4(fb[cur][u].v[i].x, sr, Xre[u]);
+          Xim[u] = mfma4(fb[cur][u].v[i].x, si, Xim[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < K1; ++u) {
+          Xre[u] = mfma4(fb[cur][u].v[i].y, si, Xre[u]);
+          Xim[u] = mfma4(-fb[cur][u].v[i].y, sr, Xim[u]);
+        }
       }
     }
-    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fa[0], fb[0]);
-    sink.template put<false>(k1t, kt2, Xre0, Xim0);
-    if (two) sink.template put<false>(k1t + 1, kt2, Xre1, Xim1);
+    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fb[0]);
+#pragma unroll
+    for (int u = 0; u < K1; ++u)
+      if (k1t + u < NB) sink.template put<false>(k1t + u, kt2, Xre[u], Xim[u]);
   }
 }
 

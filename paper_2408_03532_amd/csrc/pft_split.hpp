@@ -46,47 +46,82 @@ __device__ __forceinline__ int2 tile_rc(int tr, int tc, int i, int lane) {
   return TR ? make_int2(tr * 16 + r16, tc * 16 + 4 * g + i) : make_int2(tr * 16 + 4 * g + i, tc * 16 + r16);
 }
 
-// 8 floats (re, im interleaved) of a c4 chunk in the two product variants.
-__device__ __forceinline__ void variants_mul(const c4& a, float (&re)[8], float (&im)[8]) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    re[2 * s] = a.v[s].x;
-    re[2 * s + 1] = -a.v[s].y;
-    im[2 * s] = a.v[s].y;
-    im[2 * s + 1] = a.v[s].x;
-  }
-}
-__device__ __forceinline__ void variants_mulconj(const c4& a, float (&re)[8], float (&im)[8]) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    re[2 * s] = a.v[s].x;
-    re[2 * s + 1] = a.v[s].y;
-    im[2 * s] = a.v[s].y;
-    im[2 * s + 1] = -a.v[s].x;
-  }
-}
-
 template <class PR>
 struct SplitOp {
   typename PR::V reh, rel, imh, iml;
 };
 
 template <class PR>
-__device__ __forceinline__ SplitOp<PR> make_op(const float (&re)[8], const float (&im)[8]) {
+__device__ __forceinline__ typename PR::V pack4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(typename PR::V, (u32x4){w0, w1, w2, w3});
+}
+
+// Split operands of the two product variants of 4 complex values x:
+//   CONJ = false (x * F):        re (xr, -xi)   im (xi, xr)
+//   CONJ = true  (x * conj(F)):  re (xr, xi)    im (xi, -xr)
+// hi = RNE(v), lo = RNE(v - hi) per value (v - hi is exact in float).  Both
+// variants hold the same two numbers per dword, swapped and with one sign
+// flipped, and RNE(-v) = -RNE(v): one conversion per (xr, xi) pair, then a
+// 16-bit rotate and a sign-bit xor give the variants.
+__device__ __forceinline__ uint32_t swap16(uint32_t p) { return __builtin_amdgcn_alignbit(p, p, 16); }
+template <class PR, bool CONJ>
+__device__ __forceinline__ SplitOp<PR> split_c4(const c4& x) {
+  constexpr uint32_t kHiSign = 0x80000000u;
+  uint32_t rh[4], ih[4], rl[4], il[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float xr = x.v[s].x, xi = x.v[s].y;
+    const uint32_t h = PR::pk(xr, xi);
+    const uint32_t l = PR::pk(xr - PR::lo(h), xi - PR::hi(h));
+    if constexpr (!CONJ) {
+      rh[s] = h ^ kHiSign;
+      ih[s] = swap16(h);
+      rl[s] = l ^ kHiSign;
+      il[s] = swap16(l);
+    } else {
+      rh[s] = h;
+      ih[s] = swap16(h) ^ kHiSign;
+      rl[s] = l;
+      il[s] = swap16(l) ^ kHiSign;
+    }
+  }
   SplitOp<PR> o;
-  split8<PR>(re, o.reh, o.rel);
-  split8<PR>(im, o.imh, o.iml);
+  o.reh = pack4<PR>(rh[0], rh[1], rh[2], rh[3]);
+  o.imh = pack4<PR>(ih[0], ih[1], ih[2], ih[3]);
+  o.rel = pack4<PR>(rl[0], rl[1], rl[2], rl[3]);
+  o.iml = pack4<PR>(il[0], il[1], il[2], il[3]);
   return o;
 }
 
-// Forward, split: Y^T tiles [MT][CT] for the wave's CT column tiles.  The
-// patch chunks are fetched three blocks ahead (a 16x16x32 MFMA block is only
-// ~200 cycles of work, far shorter than a memory round trip); twiddles one
-// block ahead.
+// 4 complex values from the re / im accumulator quads.
+__device__ __forceinline__ c4 c4_of(const f32x4& re, const f32x4& im) {
+  c4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.v[i] = make_float2(re[i], im[i]);
+  return r;
+}
+
+// Forward, split: Y^T tiles [MT][CT] for the wave's CT column tiles, rows
+// strips strip0, strip0 + sstep, ...  The wave's patch chunks form one
+// sequence q = (strip index) * NB + column block, fetched kSplitRing - 1
+// chunks ahead (a chunk is ~400 cycles of products, far shorter than a
+// memory round trip); twiddles one chunk ahead.  The operand split of chunk
+// q + 1 is issued between the products of chunk q, so the vector ALU work
+// runs beside the matrix cores instead of before them.  When NB is a
+// multiple of the ring the sequence runs on across strips (no refill at a
+// strip start); otherwise the ring restarts per strip.  The ring size must
+// be even (twiddle and operand ping-pong).
+#ifndef PFTPIE_SPLIT_RING
+#define PFTPIE_SPLIT_RING 8
+#endif
+constexpr int kSplitRing = PFTPIE_SPLIT_RING;
 template <class PR, int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab& FA, int c2t0,
                                                f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
-                                               int sstep = 1) {
+                                               int sstep = 1, int rot = 0) {
+  static_assert(kSplitRing % 2 == 0, "ring size must be even");
+  constexpr int RING = kSplitRing;
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -96,79 +131,123 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
       Yre[a][b] = zero4();
       Yim[a][b] = zero4();
     }
-  for (int strip = strip0; strip < NB; strip += sstep) {
-    const int row = strip * 16 + r16;
-    f32x4 Tre[CT], Tim[CT];
+  const int nstrips = strip0 < NB ? (NB - strip0 + sstep - 1) / sstep : 0;
+  if (nstrips == 0) return;
+  f32x4 Tre[CT], Tim[CT];
+  auto products = [&](const SplitOp<PR>& op, const TwS<PR>(&f)[CT]) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      Tre[ct] = PR::mfma(op.reh, f[ct].h, Tre[ct]);
+      Tim[ct] = PR::mfma(op.imh, f[ct].h, Tim[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      Tre[ct] = PR::mfma(op.reh, f[ct].l, Tre[ct]);
+      Tim[ct] = PR::mfma(op.imh, f[ct].l, Tim[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      Tre[ct] = PR::mfma(op.rel, f[ct].h, Tre[ct]);
+      Tim[ct] = PR::mfma(op.iml, f[ct].h, Tim[ct]);
+    }
+  };
+  // stage 2 (transposed): Y^T[c2][c1] += sum_{k1 in strip} T[k1][c2] F[c1][k1]
+  auto stage2 = [&](int strip) {
+    TwS<PR> fb[MT];
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) fb[c1t] = FA.template s16<PR>((size_t)c1t * NB + strip, lane);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const SplitOp<PR> op = split_c4<PR, false>(c4_of(Tre[ct], Tim[ct]));
+#pragma unroll
+      for (int c1t = 0; c1t < MT; ++c1t) {
+        Yre[c1t][ct] = PR::mfma(op.reh, fb[c1t].h, Yre[c1t][ct]);
+        Yim[c1t][ct] = PR::mfma(op.imh, fb[c1t].h, Yim[c1t][ct]);
+        Yre[c1t][ct] = PR::mfma(op.reh, fb[c1t].l, Yre[c1t][ct]);
+        Yim[c1t][ct] = PR::mfma(op.imh, fb[c1t].l, Yim[c1t][ct]);
+        Yre[c1t][ct] = PR::mfma(op.rel, fb[c1t].h, Yre[c1t][ct]);
+        Yim[c1t][ct] = PR::mfma(op.iml, fb[c1t].h, Yim[c1t][ct]);
+      }
+    }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       Tre[ct] = zero4();
       Tim[ct] = zero4();
     }
-    auto stage1 = [&](const c4& a, const TwS<PR>(&f)[CT]) {
-      float re[8], im[8];
-      variants_mul(a, re, im);
-      const SplitOp<PR> op = make_op<PR>(re, im);
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        Tre[ct] = PR::mfma(op.reh, f[ct].h, Tre[ct]);
-        Tim[ct] = PR::mfma(op.imh, f[ct].h, Tim[ct]);
-      }
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        Tre[ct] = PR::mfma(op.reh, f[ct].l, Tre[ct]);
-        Tim[ct] = PR::mfma(op.imh, f[ct].l, Tim[ct]);
-      }
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        Tre[ct] = PR::mfma(op.rel, f[ct].h, Tre[ct]);
-        Tim[ct] = PR::mfma(op.iml, f[ct].h, Tim[ct]);
-      }
-    };
-    auto load_a = [&](int kb) { return src.load(row, (kb < NB ? kb : NB - 1) * 16 + 4 * g); };
-    auto load_f = [&](int kb, TwS<PR>(&f)[CT]) {
-      const int k = kb < NB ? kb : NB - 1;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) f[ct] = FA.template s16<PR>((size_t)(c2t0 + ct) * NB + k, lane);
-    };
-    c4 a[4];
-    TwS<PR> f[2][CT];
-    a[0] = load_a(0);
-    a[1] = load_a(1);
-    a[2] = load_a(2);
-    load_f(0, f[0]);
-    for (int kb = 0; kb < NB; kb += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (kb + u < NB) {
-          a[(u + 3) & 3] = load_a(kb + u + 3);
-          load_f(kb + u + 1, f[(u + 1) & 1]);
-          __builtin_amdgcn_sched_barrier(0);
-          stage1(a[u], f[u & 1]);
-        }
-      }
-    }
-    // stage 2 (transposed): Y^T[c2][c1] += sum_{k1 in strip} T[k1][c2] F[c1][k1]
+  };
+  c4 a[RING];
+  TwS<PR> f[2][CT];
+  SplitOp<PR> op[2];
+  // one chunk step of a ring turn starting at chunk q0 (q0 % RING == 0 within
+  // the sequence the loaders index): request chunk q0 + u + RING - 1 and the
+  // next twiddles, split chunk q0 + u + 1, multiply chunk q0 + u
+  auto run = [&](auto load_a, auto load_f, int q0, int u) {
+    a[(u + RING - 1) % RING] = load_a(q0 + u + RING - 1);
+    load_f(q0 + u + 1, f[(u + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    op[(u + 1) & 1] = split_c4<PR, false>(a[(u + 1) % RING]);
+    products(op[u & 1], f[u & 1]);
+  };
+  auto start = [&](auto load_a, auto load_f) {
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      float re[8], im[8];
+      Tre[ct] = zero4();
+      Tim[ct] = zero4();
+    }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        re[2 * i] = Tre[ct][i];
-        re[2 * i + 1] = -Tim[ct][i];
-        im[2 * i] = Tim[ct][i];
-        im[2 * i + 1] = Tre[ct][i];
-      }
-      const SplitOp<PR> op = make_op<PR>(re, im);
+    for (int u = 0; u < RING - 1; ++u) a[u] = load_a(u);
+    load_f(0, f[0]);
+    op[0] = split_c4<PR, false>(a[0]);
+  };
+  if (NB % RING == 0) {
+    // one sequence over all the wave's strips; whole ring turns carry no
+    // guard (a guarded load makes the wait-count analysis assume the loads
+    // after it were skipped and drain the ring every turn)
+    // column blocks in the order rot, rot + 1, ... (mod NB): waves that start
+    // at different offsets of their patches spread over the memory channels
+    const int nq = nstrips * NB;
+    auto load_a = [&](int q) {
+      q = q < nq ? q : nq - 1;
+      const int j = q / NB;
+      int k = q - j * NB + rot;
+      k = k < NB ? k : k - NB;
+      return src.load((strip0 + j * sstep) * 16 + r16, k * 16 + 4 * g);
+    };
+    auto load_f = [&](int q, TwS<PR>(&fr)[CT]) {
+      int k = (q < nq ? q : nq - 1) % NB + rot;
+      k = k < NB ? k : k - NB;
 #pragma unroll
-      for (int c1t = 0; c1t < MT; ++c1t) {
-        const TwS<PR> fb = FA.template s16<PR>((size_t)c1t * NB + strip, lane);
-        Yre[c1t][ct] = PR::mfma(op.reh, fb.h, Yre[c1t][ct]);
-        Yim[c1t][ct] = PR::mfma(op.imh, fb.h, Yim[c1t][ct]);
-        Yre[c1t][ct] = PR::mfma(op.reh, fb.l, Yre[c1t][ct]);
-        Yim[c1t][ct] = PR::mfma(op.imh, fb.l, Yim[c1t][ct]);
-        Yre[c1t][ct] = PR::mfma(op.rel, fb.h, Yre[c1t][ct]);
-        Yim[c1t][ct] = PR::mfma(op.iml, fb.h, Yim[c1t][ct]);
+      for (int ct = 0; ct < CT; ++ct) fr[ct] = FA.template s16<PR>((size_t)(c2t0 + ct) * NB + k, lane);
+    };
+    start(load_a, load_f);
+    for (int j = 0; j < nstrips; ++j) {
+      for (int q0 = j * NB; q0 < (j + 1) * NB; q0 += RING) {
+#pragma unroll
+        for (int u = 0; u < RING; ++u) run(load_a, load_f, q0, u);
       }
+      stage2(strip0 + j * sstep);
+    }
+  } else {
+    for (int strip = strip0; strip < NB; strip += sstep) {
+      const int row = strip * 16 + r16;
+      auto load_a = [&](int kb) { return src.load(row, (kb < NB ? kb : NB - 1) * 16 + 4 * g); };
+      auto load_f = [&](int kb, TwS<PR>(&fr)[CT]) {
+        const int k = kb < NB ? kb : NB - 1;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) fr[ct] = FA.template s16<PR>((size_t)(c2t0 + ct) * NB + k, lane);
+      };
+      start(load_a, load_f);
+      int kb = 0;
+      for (; kb + RING <= NB; kb += RING) {
+#pragma unroll
+        for (int u = 0; u < RING; ++u) run(load_a, load_f, kb, u);
+      }
+      if (kb < NB) {
+#pragma unroll
+        for (int u = 0; u < RING; ++u)
+          if (kb + u < NB) run(load_a, load_f, kb, u);
+      }
+      stage2(strip);
     }
   }
 }
@@ -185,18 +264,13 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
     Sre[a] = zero4();
     Sim[a] = zero4();
   }
-  // stage 1: S[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2])
-#pragma unroll
-  for (int kb = 0; kb < MT; ++kb) {
-    const TwS<PR> f = FT.template s16<PR>((size_t)kt2 * MT + kb, lane);
-    c4 y[MT];
-#pragma unroll
-    for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+  // stage 1: S[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2]); coefficient
+  // chunks of the next column block are fetched while this block's products
+  // issue (ping-pong for MT <= 4)
+  auto stage1 = [&](const TwS<PR>& f, const c4(&y)[MT]) {
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
-      float re[8], im[8];
-      variants_mulconj(y[c1t], re, im);
-      const SplitOp<PR> op = make_op<PR>(re, im);
+      const SplitOp<PR> op = split_c4<PR, true>(y[c1t]);
       Sre[c1t] = PR::mfma(op.reh, f.h, Sre[c1t]);
       Sim[c1t] = PR::mfma(op.imh, f.h, Sim[c1t]);
       Sre[c1t] = PR::mfma(op.reh, f.l, Sre[c1t]);
@@ -204,20 +278,36 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
       Sre[c1t] = PR::mfma(op.rel, f.h, Sre[c1t]);
       Sim[c1t] = PR::mfma(op.iml, f.h, Sim[c1t]);
     }
+  };
+  auto fetch1 = [&](int kb, TwS<PR>& f, c4(&y)[MT]) {
+    f = FT.template s16<PR>((size_t)kt2 * MT + kb, lane);
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+  };
+  if constexpr (MT <= 4) {
+    TwS<PR> f[2];
+    c4 y[2][MT];
+    fetch1(0, f[0], y[0]);
+#pragma unroll
+    for (int kb = 0; kb < MT; ++kb) {
+      if (kb + 1 < MT) fetch1(kb + 1, f[(kb + 1) & 1], y[(kb + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(f[kb & 1], y[kb & 1]);
+    }
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < MT; ++kb) {
+      TwS<PR> f;
+      c4 y[MT];
+      fetch1(kb, f, y);
+      stage1(f, y);
+    }
   }
   // stage-2 operands from the accumulators: S^T rows (k2) x c1, times conj(F)
   SplitOp<PR> ops[MT];
 #pragma unroll
   for (int c1t = 0; c1t < MT; ++c1t) {
-    float re[8], im[8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      re[2 * i] = Sre[c1t][i];
-      re[2 * i + 1] = Sim[c1t][i];
-      im[2 * i] = Sim[c1t][i];
-      im[2 * i + 1] = -Sre[c1t][i];
-    }
-    ops[c1t] = make_op<PR>(re, im);
+    ops[c1t] = split_c4<PR, true>(c4_of(Sre[c1t], Sim[c1t]));
   }
   // stage 2 (transposed): X^T[k2][k1] = sum_c1 S[c1][k2] conj(F[c1][k1]),
   // two row tiles at a time, ping-pong twiddle fetches
@@ -266,19 +356,19 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
 template <class PR, int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_engine(const Src& src, int NB, const Tab& FA, int c2t0,
                                            f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
-                                           int sstep = 1) {
+                                           int sstep = 1, int rot = 0) {
   if constexpr (Orient<PR>::TR)
-    fwd_wave_split<PR, MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
+    fwd_wave_split<PR, MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, rot);
   else
     fwd_wave<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
 }
 
-template <class PR, int MT, class YSrc, class Sink, class Tab>
+template <class PR, int MT, class YSrc, class Sink, class Tab, int K1 = 2>
 __device__ __forceinline__ void adj_engine(const YSrc& ysrc, int NB, const Tab& FT, int kt2, Sink& sink) {
   if constexpr (Orient<PR>::TR)
     adj_wave_tile_split<PR, MT>(ysrc, NB, FT, kt2, sink);
   else
-    adj_wave_tile<MT>(ysrc, NB, FT, kt2, sink);
+    adj_wave_tile<MT, YSrc, Sink, Tab, K1>(ysrc, NB, FT, kt2, sink);
 }
 
 template <class Tab>

@@ -84,9 +84,13 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
   p->nb = ceil16(n);
   p->mt = ceil16(m);
   p->fa_ctiles = fa_ctiles_for(p->mt);
-  p->fwd_ct = fwd_ct_default(p->mt);
+  p->fwd_ct = prec == PFTPIE_FP32 ? fwd_ct_default(p->mt) : fwd_ct_default_split(p->mt);
   p->use_lds = 1;
   p->use_lds_adj = 1;
+  p->adj_k1 = 2;
+  if (const char* env = std::getenv("PFTPIE_ADJ_K1")) p->adj_k1 = std::atoi(env) == 4 ? 4 : 2;
+  p->adj_threads = 512;
+  if (const char* env = std::getenv("PFTPIE_ADJ_THREADS")) p->adj_threads = std::atoi(env) == 768 ? 768 : 512;
   if (const char* env = std::getenv("PFTPIE_LDS")) p->use_lds = p->use_lds_adj = std::atoi(env) != 0;
   if (const char* env = std::getenv("PFTPIE_FWD_CT")) {  // tuning override
     const int ct = std::atoi(env);
