@@ -43,6 +43,7 @@ struct pftpie_plan_s {
   int use_lds_adj;   // persistent LDS-table kernel for the plain adjoint
   int adj_k1;        // FP32 adjoint: row tiles per stage-2 step (2 or 4)
   int adj_threads;   // FP32 persistent adjoint: threads per workgroup (512 or 768)
+  int adj_patch;     // split adjoint: whole patch per wave when m <= 64 (else tile per wave)
   int num_cu;        // compute units of the plan's device
   int device;
   void* fa;          // device FA table (float4 blocks, or split 16-bit blocks)

@@ -77,6 +77,39 @@ struct StoreSink {
   }
 };
 
+// Sink of transposed-orientation tiles (element i of lane (r, g) at row
+// 16 k1t + r, column 16 k2t + 4 g + i) for n % 16 == 0 and 16-byte aligned
+// output.  Lanes r and r + 8 of each 16-lane row swap one half of their four
+// values (row rotate by 8), so each of the two 16-byte-per-lane stores
+// writes 8 whole 128-byte tile rows instead of half of 16.
+struct StoreSinkRows {
+  float2* __restrict__ out;
+  int n;
+  template <bool TR>
+  __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& re, const f32x4& im) const {
+    static_assert(TR, "row stores serve the transposed tile orientation");
+    const int lane = lane_id();
+    const int r16 = lane & 15, g = lane >> 4;
+    const bool upper = r16 >= 8;
+    const float a[4] = {re[0], im[0], re[1], im[1]};  // columns 4g, 4g+1
+    const float b[4] = {re[2], im[2], re[3], im[3]};  // columns 4g+2, 4g+3
+    float r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float snd = upper ? a[k] : b[k];
+      r[k] = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, snd), 0x128, 0xf, 0xf, false));
+    }
+    // lane r < 8: row r columns 4g.. (own a), row r + 8 columns 4g.. (partner's a)
+    // lane r >= 8: row r - 8 columns 4g+2.. (partner's b), row r columns 4g+2.. (own b)
+    const int row = k1t * 16 + (r16 & 7);
+    const int col = k2t * 16 + 4 * g + 2 * (r16 >> 3);
+    float4* q0 = reinterpret_cast<float4*>(out + (size_t)row * n + col);
+    float4* q1 = reinterpret_cast<float4*>(out + (size_t)(row + 8) * n + col);
+    *q0 = upper ? make_float4(r[0], r[1], r[2], r[3]) : make_float4(a[0], a[1], a[2], a[3]);
+    *q1 = upper ? make_float4(b[0], b[1], b[2], b[3]) : make_float4(r[0], r[1], r[2], r[3]);
+  }
+};
+
 // Adjoint: one workgroup of W waves per patch; wave w takes column tiles
 // w, w + W, ...
 template <class PR, int MT>
@@ -149,6 +182,45 @@ __global__ __launch_bounds__(THREADS) void k_adjoint_lds(const float2* __restric
       CoefSrc src{y + b * (int64_t)m * m, m};
       adj_engine<PR, MT, CoefSrc, StoreSink, TabL, K1>(src, nb, T, kt2, sink);
     }
+  }
+}
+
+// Split adjoint, whole patch per wave (m <= 64, m % 16 == 0, n % 16 == 0,
+// 16-byte aligned).  At m = 48, 64 the split coefficients of a patch take
+// most of the register file: 256-thread workgroups, one wave per SIMD; at
+// m <= 32 two waves per SIMD fit.
+template <int MT>
+constexpr int adj_patch_threads() { return MT <= 2 ? 512 : 256; }
+template <class PR, int MT, int THREADS = adj_patch_threads<MT>()>
+__global__ __launch_bounds__(THREADS) void k_adjoint_patch_lds(const float2* __restrict__ y,
+                                                                   float2* __restrict__ psi, int n, int m, int nb,
+                                                                   const f32x4* __restrict__ tab, int tab16,
+                                                                   int64_t batch) {
+  extern __shared__ f32x4 smem[];
+  copy_table_to_lds(smem, tab, tab16);
+  const TabL T{(lds_cptr)smem};
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int64_t b = (int64_t)blockIdx.x * nwaves + wave; b < batch; b += (int64_t)gridDim.x * nwaves) {
+    CoefSrcExact src{y + b * (int64_t)m * m, m};
+    StoreSinkRows sink{psi + b * (int64_t)n * n, n};
+    adj_patch_split<PR, MT>(src, nb, T, sink);
+  }
+}
+
+// FP32 adjoint, whole patch per wave (m <= 64, m % 16 == 0): the raw
+// coefficients take 8 MT^2 registers, so two waves per SIMD still fit.
+template <int MT, int K1>
+__global__ __launch_bounds__(512) void k_adjoint_patch_f32_lds(const float2* __restrict__ y, float2* __restrict__ psi,
+                                                                 int n, int m, int nb, const f32x4* __restrict__ tab,
+                                                                 int tab16, int64_t batch) {
+  extern __shared__ f32x4 smem[];
+  copy_table_to_lds(smem, tab, tab16);
+  const TabL T{(lds_cptr)smem};
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int64_t b = (int64_t)blockIdx.x * nwaves + wave; b < batch; b += (int64_t)gridDim.x * nwaves) {
+    CoefSrcExact src{y + b * (int64_t)m * m, m};
+    StoreSink sink{psi + b * (int64_t)n * n, n};
+    adj_patch_f32<MT, K1>(src, nb, T, sink);
   }
 }
 
@@ -232,6 +304,17 @@ static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, i
   if (p->use_lds_adj && p->ft_bytes <= kMaxLdsTable) {
     const int64_t items = batch * p->nb;
     const bool exact = (p->m % 16 == 0) && ((uintptr_t)y % 16 == 0);
+    if constexpr (MT <= 4) {
+      // (two stage-2 row tiles per step: four would spill at m = 64)
+      if (p->prec == PFTPIE_FP32 && exact && p->adj_patch)
+        return launch_lds(k_adjoint_patch_f32_lds<MT, 2>, p, p->ft_bytes, batch, st, y, psi, p->ft, batch, 512);
+      if (p->prec != PFTPIE_FP32 && exact && p->adj_patch && p->n % 16 == 0 && (uintptr_t)psi % 16 == 0)
+        return p->prec == PFTPIE_SPLIT_BF16
+                   ? launch_lds(k_adjoint_patch_lds<PrecBF16, MT>, p, p->ft_bytes, batch, st, y, psi, p->ft, batch,
+                                adj_patch_threads<MT>())
+                   : launch_lds(k_adjoint_patch_lds<PrecF16, MT>, p, p->ft_bytes, batch, st, y, psi, p->ft, batch,
+                                adj_patch_threads<MT>());
+    }
     if (p->prec == PFTPIE_SPLIT_BF16)
       return exact ? launch_lds(k_adjoint_lds<PrecBF16, MT, true, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch)
                    : launch_lds(k_adjoint_lds<PrecBF16, MT, false, 2>, p, p->ft_bytes, items, st, y, psi, p->ft, batch);

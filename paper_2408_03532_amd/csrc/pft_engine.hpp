@@ -133,6 +133,61 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
   }
 }
 
+// FP32 adjoint, stage 2 of column tile kt2 from the stage-1 accumulators S.
+template <int MT, int K1, class Sink, class Tab>
+__device__ __forceinline__ void adj_stage2_f32(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,
+                                               int kt2, Sink& sink) {
+  const int lane = lane_id();
+  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], K1 row tiles at a
+  // time; the twiddle blocks of the next step are fetched while the current
+  // step's products issue (ping-pong buffers, no register copies).
+  auto fetch2 = [&](int k1t, int c1t, c4(&f)[K1]) {
+#pragma unroll
+    for (int u = 0; u < K1; ++u) {
+      const int kt = (k1t + u < NB) ? k1t + u : NB - 1;
+      f[u] = FT.f32((size_t)kt * MT + c1t, lane);
+    }
+  };
+  c4 fb[2][K1];
+  fetch2(0, 0, fb[0]);
+  for (int k1t = 0; k1t < NB; k1t += K1) {
+    const int k1n = (k1t + K1 < NB) ? k1t + K1 : k1t;
+    f32x4 Xre[K1], Xim[K1];
+#pragma unroll
+    for (int u = 0; u < K1; ++u) {
+      Xre[u] = zero4();
+      Xim[u] = zero4();
+    }
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      const int cur = c1t & 1;
+      if (c1t + 1 < MT)
+        fetch2(k1t, c1t + 1, fb[cur ^ 1]);
+      else if ((MT & 1) == 0)
+        fetch2(k1n, 0, fb[cur ^ 1]);  // cur ^ 1 == 0 here
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float sr = Sre[c1t][i], si = Sim[c1t][i];
+#pragma unroll
+        for (int u = 0; u < K1; ++u) {
+          Xre[u] = mfma4(fb[cur][u].v[i].x, sr, Xre[u]);
+          Xim[u] = mfma4(fb[cur][u].v[i].x, si, Xim[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < K1; ++u) {
+          Xre[u] = mfma4(fb[cur][u].v[i].y, si, Xre[u]);
+          Xim[u] = mfma4(-fb[cur][u].v[i].y, sr, Xim[u]);
+        }
+      }
+    }
+    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fb[0]);
+#pragma unroll
+    for (int u = 0; u < K1; ++u)
+      if (k1t + u < NB) sink.template put<false>(k1t + u, kt2, Xre[u], Xim[u]);
+  }
+}
+
 // Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
 // returns Y[row][col0..col0+3] (zeros outside m x m).  FT holds NB x MT
 // blocks.  sink.put<false>(k1t, kt2, Xre, Xim) receives each finished tile.
@@ -185,53 +240,51 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Ta
       stage1(f, y);
     }
   }
-  // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], K1 row tiles at a
-  // time; the twiddle blocks of the next step are fetched while the current
-  // step's products issue (ping-pong buffers, no register copies).
-  auto fetch2 = [&](int k1t, int c1t, c4(&f)[K1]) {
+  adj_stage2_f32<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
+}
+
+// FP32 adjoint, one whole patch per wave (MT <= 4): the m x m coefficients
+// stay in registers (128 at MT = 4) for every column tile kt2, so the wave
+// issues no memory loads between its output stores.
+template <int MT, int K1, class YSrc, class Sink, class Tab>
+__device__ __forceinline__ void adj_patch_f32(const YSrc& ysrc, int NB, const Tab& FT, Sink& sink) {
+  static_assert(MT <= 4, "larger windows do not fit in registers");
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+  c4 y[MT][MT];  // [column block kb][row tile c1t]
 #pragma unroll
-    for (int u = 0; u < K1; ++u) {
-      const int kt = (k1t + u < NB) ? k1t + u : NB - 1;
-      f[u] = FT.f32((size_t)kt * MT + c1t, lane);
+  for (int kb = 0; kb < MT; ++kb)
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) y[kb][c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+  for (int kt2 = 0; kt2 < NB; ++kt2) {
+    f32x4 Sre[MT], Sim[MT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      Sre[a] = zero4();
+      Sim[a] = zero4();
     }
-  };
-  c4 fb[2][K1];
-  fetch2(0, 0, fb[0]);
-  for (int k1t = 0; k1t < NB; k1t += K1) {
-    const int k1n = (k1t + K1 < NB) ? k1t + K1 : k1t;
-    f32x4 Xre[K1], Xim[K1];
+    c4 f[2];
+    f[0] = FT.f32((size_t)kt2 * MT, lane);
 #pragma unroll
-    for (int u = 0; u < K1; ++u) {
-      Xre[u] = zero4();
-      Xim[u] = zero4();
-    }
+    for (int kb = 0; kb < MT; ++kb) {
+      if (kb + 1 < MT) f[(kb + 1) & 1] = FT.f32((size_t)kt2 * MT + kb + 1, lane);
+      const c4& fc = f[kb & 1];
 #pragma unroll
-    for (int c1t = 0; c1t < MT; ++c1t) {
-      const int cur = c1t & 1;
-      if (c1t + 1 < MT)
-        fetch2(k1t, c1t + 1, fb[cur ^ 1]);
-      else if ((MT & 1) == 0)
-        fetch2(k1n, 0, fb[cur ^ 1]);  // cur ^ 1 == 0 here
-      __builtin_amdgcn_sched_barrier(0);
+      for (int s = 0; s < 4; ++s) {
+        const float fr = fc.v[s].x, fi = fc.v[s].y;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float sr = Sre[c1t][i], si = Sim[c1t][i];
-#pragma unroll
-        for (int u = 0; u < K1; ++u) {
-          Xre[u] = mfma4(fb[cur][u].v[i].x, sr, Xre[u]);
-          Xim[u] = mfma4(fb[cur][u].v[i].x, si, Xim[u]);
+        for (int c1t = 0; c1t < MT; ++c1t) {
+          Sre[c1t] = mfma4(y[kb][c1t].v[s].x, fr, Sre[c1t]);
+          Sim[c1t] = mfma4(y[kb][c1t].v[s].y, fr, Sim[c1t]);
         }
 #pragma unroll
-        for (int u = 0; u < K1; ++u) {
-          Xre[u] = mfma4(fb[cur][u].v[i].y, si, Xre[u]);
-          Xim[u] = mfma4(-fb[cur][u].v[i].y, sr, Xim[u]);
+        for (int c1t = 0; c1t < MT; ++c1t) {
+          Sre[c1t] = mfma4(y[kb][c1t].v[s].y, fi, Sre[c1t]);
+          Sim[c1t] = mfma4(-y[kb][c1t].v[s].x, fi, Sim[c1t]);
         }
       }
     }
-    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fb[0]);
-#pragma unroll
-    for (int u = 0; u < K1; ++u)
-      if (k1t + u < NB) sink.template put<false>(k1t + u, kt2, Xre[u], Xim[u]);
+    adj_stage2_f32<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
   }
 }
 

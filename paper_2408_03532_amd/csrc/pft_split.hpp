@@ -252,6 +252,53 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
   }
 }
 
+// Split adjoint, stage 2 (transposed) of column tile kt2 from the split
+// stage-1 operands: X^T[k2][k1] = sum_c1 S[c1][k2] conj(F[c1][k1]), two row
+// tiles at a time with ping-pong twiddle fetches; sink.put<true> receives
+// the X^T tiles.
+template <class PR, int MT, class Sink, class Tab>
+__device__ __forceinline__ void adj_stage2_split(const SplitOp<PR> (&ops)[MT], int NB, const Tab& FT, int kt2,
+                                                 Sink& sink) {
+  const int lane = lane_id();
+  auto fetch2 = [&](int k1t, int c1t, TwS<PR>& fa, TwS<PR>& fb) {
+    const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
+    fa = FT.template s16<PR>((size_t)k1t * MT + c1t, lane);
+    fb = FT.template s16<PR>((size_t)k1b * MT + c1t, lane);
+  };
+  TwS<PR> fa[2], fb[2];
+  fetch2(0, 0, fa[0], fb[0]);
+  for (int k1t = 0; k1t < NB; k1t += 2) {
+    const bool two = (k1t + 1 < NB);
+    const int k1n = (k1t + 2 < NB) ? k1t + 2 : k1t;
+    f32x4 Xre0 = zero4(), Xim0 = zero4(), Xre1 = zero4(), Xim1 = zero4();
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      const int cur = c1t & 1;
+      if (c1t + 1 < MT)
+        fetch2(k1t, c1t + 1, fa[cur ^ 1], fb[cur ^ 1]);
+      else if ((MT & 1) == 0)
+        fetch2(k1n, 0, fa[cur ^ 1], fb[cur ^ 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      const SplitOp<PR>& o = ops[c1t];
+      Xre0 = PR::mfma(o.reh, fa[cur].h, Xre0);
+      Xim0 = PR::mfma(o.imh, fa[cur].h, Xim0);
+      Xre1 = PR::mfma(o.reh, fb[cur].h, Xre1);
+      Xim1 = PR::mfma(o.imh, fb[cur].h, Xim1);
+      Xre0 = PR::mfma(o.reh, fa[cur].l, Xre0);
+      Xim0 = PR::mfma(o.imh, fa[cur].l, Xim0);
+      Xre1 = PR::mfma(o.reh, fb[cur].l, Xre1);
+      Xim1 = PR::mfma(o.imh, fb[cur].l, Xim1);
+      Xre0 = PR::mfma(o.rel, fa[cur].h, Xre0);
+      Xim0 = PR::mfma(o.iml, fa[cur].h, Xim0);
+      Xre1 = PR::mfma(o.rel, fb[cur].h, Xre1);
+      Xim1 = PR::mfma(o.iml, fb[cur].h, Xim1);
+    }
+    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fa[0], fb[0]);
+    sink.template put<true>(k1t, kt2, Xre0, Xim0);
+    if (two) sink.template put<true>(k1t + 1, kt2, Xre1, Xim1);
+  }
+}
+
 // Adjoint, split, one column tile kt2: sink.put<true> receives X^T tiles.
 template <class PR, int MT, class YSrc, class Sink, class Tab>
 __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, const Tab& FT, int kt2,
@@ -309,48 +356,56 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
   for (int c1t = 0; c1t < MT; ++c1t) {
     ops[c1t] = split_c4<PR, true>(c4_of(Sre[c1t], Sim[c1t]));
   }
-  // stage 2 (transposed): X^T[k2][k1] = sum_c1 S[c1][k2] conj(F[c1][k1]),
-  // two row tiles at a time, ping-pong twiddle fetches
-  auto fetch2 = [&](int k1t, int c1t, TwS<PR>& fa, TwS<PR>& fb) {
-    const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
-    fa = FT.template s16<PR>((size_t)k1t * MT + c1t, lane);
-    fb = FT.template s16<PR>((size_t)k1b * MT + c1t, lane);
-  };
-  TwS<PR> fa[2], fb[2];
-  fetch2(0, 0, fa[0], fb[0]);
-  for (int k1t = 0; k1t < NB; k1t += 2) {
-    const bool two = (k1t + 1 < NB);
-    const int k1n = (k1t + 2 < NB) ? k1t + 2 : k1t;
-    f32x4 Xre0 = zero4(), Xim0 = zero4(), Xre1 = zero4(), Xim1 = zero4();
-#pragma unroll
-    for (int c1t = 0; c1t < MT; ++c1t) {
-      const int cur = c1t & 1;
-      if (c1t + 1 < MT)
-        fetch2(k1t, c1t + 1, fa[cur ^ 1], fb[cur ^ 1]);
-      else if ((MT & 1) == 0)
-        fetch2(k1n, 0, fa[cur ^ 1], fb[cur ^ 1]);
-      __builtin_amdgcn_sched_barrier(0);
-      const SplitOp<PR>& o = ops[c1t];
-      Xre0 = PR::mfma(o.reh, fa[cur].h, Xre0);
-      Xim0 = PR::mfma(o.imh, fa[cur].h, Xim0);
-      Xre1 = PR::mfma(o.reh, fb[cur].h, Xre1);
-      Xim1 = PR::mfma(o.imh, fb[cur].h, Xim1);
-      Xre0 = PR::mfma(o.reh, fa[cur].l, Xre0);
-      Xim0 = PR::mfma(o.imh, fa[cur].l, Xim0);
-      Xre1 = PR::mfma(o.reh, fb[cur].l, Xre1);
-      Xim1 = PR::mfma(o.imh, fb[cur].l, Xim1);
-      Xre0 = PR::mfma(o.rel, fa[cur].h, Xre0);
-      Xim0 = PR::mfma(o.iml, fa[cur].h, Xim0);
-      Xre1 = PR::mfma(o.rel, fb[cur].h, Xre1);
-      Xim1 = PR::mfma(o.iml, fb[cur].h, Xim1);
-    }
-    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fa[0], fb[0]);
-    sink.template put<true>(k1t, kt2, Xre0, Xim0);
-    if (two) sink.template put<true>(k1t + 1, kt2, Xre1, Xim1);
-  }
+  adj_stage2_split<PR, MT>(ops, NB, FT, kt2, sink);
 }
 
 // ---------------------------------------------------------------------------
+// Split adjoint, one whole patch per wave (MT <= 4): the m x m coefficients
+// are loaded and split once (MT * MT operands, 256 registers at MT = 4) and
+// serve every column tile kt2, so the wave issues no memory loads between
+// its output stores and the stage-1 operand split is not repeated per tile.
+template <class PR, int MT, class YSrc, class Sink, class Tab>
+__device__ __forceinline__ void adj_patch_split(const YSrc& ysrc, int NB, const Tab& FT, Sink& sink) {
+  static_assert(MT <= 4, "the split coefficients of larger windows do not fit in registers");
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+  SplitOp<PR> ys[MT][MT];  // [column block kb][row tile c1t]
+#pragma unroll
+  for (int kb = 0; kb < MT; ++kb)
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) ys[kb][c1t] = split_c4<PR, true>(ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g));
+  for (int kt2 = 0; kt2 < NB; ++kt2) {
+    // stage 1: S[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2]) for this tile
+    f32x4 Sre[MT], Sim[MT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      Sre[a] = zero4();
+      Sim[a] = zero4();
+    }
+    TwS<PR> f[2];
+    f[0] = FT.template s16<PR>((size_t)kt2 * MT, lane);
+#pragma unroll
+    for (int kb = 0; kb < MT; ++kb) {
+      if (kb + 1 < MT) f[(kb + 1) & 1] = FT.template s16<PR>((size_t)kt2 * MT + kb + 1, lane);
+      const TwS<PR>& fc = f[kb & 1];
+#pragma unroll
+      for (int c1t = 0; c1t < MT; ++c1t) {
+        const SplitOp<PR>& op = ys[kb][c1t];
+        Sre[c1t] = PR::mfma(op.reh, fc.h, Sre[c1t]);
+        Sim[c1t] = PR::mfma(op.imh, fc.h, Sim[c1t]);
+        Sre[c1t] = PR::mfma(op.reh, fc.l, Sre[c1t]);
+        Sim[c1t] = PR::mfma(op.imh, fc.l, Sim[c1t]);
+        Sre[c1t] = PR::mfma(op.rel, fc.h, Sre[c1t]);
+        Sim[c1t] = PR::mfma(op.iml, fc.h, Sim[c1t]);
+      }
+    }
+    SplitOp<PR> ops[MT];
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) ops[c1t] = split_c4<PR, true>(c4_of(Sre[c1t], Sim[c1t]));
+    adj_stage2_split<PR, MT>(ops, NB, FT, kt2, sink);
+  }
+}
+
 // precision-generic entry points used by the kernels
 
 template <class PR, int MT, int CT, class Src, class Tab>

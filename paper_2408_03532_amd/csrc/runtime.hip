@@ -89,6 +89,8 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
   p->use_lds_adj = 1;
   p->adj_k1 = 2;
   if (const char* env = std::getenv("PFTPIE_ADJ_K1")) p->adj_k1 = std::atoi(env) == 4 ? 4 : 2;
+  p->adj_patch = 1;
+  if (const char* env = std::getenv("PFTPIE_ADJ_PATCH")) p->adj_patch = std::atoi(env) != 0;
   p->adj_threads = 512;
   if (const char* env = std::getenv("PFTPIE_ADJ_THREADS")) p->adj_threads = std::atoi(env) == 768 ? 768 : 512;
   if (const char* env = std::getenv("PFTPIE_LDS")) p->use_lds = p->use_lds_adj = std::atoi(env) != 0;
