@@ -147,21 +147,23 @@ def cpu_baseline(n, m, gpu_out, seconds):
                        f"batch, cycled) in {el:.1f} s, numpy complex128"}, errs)
 
 
-def pie_at_scale_rate(torch, pk, precision, sweeps=10, warmup=2):
-    """Phase-1 sweeps of the warm-started workload (1024^2 object, 128^2
-    probe, 900 positions, m = 32, fully batched, overlap-normalised)."""
+def pie_at_scale_rate(torch, pk, precision, sweeps=10, warmup=2, m=32, method="auto"):
+    """Sweeps of the warm-started workload (1024^2 object, 128^2 probe, 900
+    positions, fully batched, overlap-normalised): phase 1 at m = 32, or the
+    full-resolution phase 2 at m = 128 (method "auto": the fast full-window
+    transform; "dense": the contraction at m = n)."""
     import workloads
     case = workloads.pie_at_scale()
-    scan = pk.Scan(case["pos"], (1024, 1024), 128, 32, precision=precision)
+    scan = pk.Scan(case["pos"], (1024, 1024), 128, m, precision=precision, method=method)
     I = torch.from_numpy(case["intensity"]).cuda()
-    amp = pk.crop_amplitudes(I, 32)
+    amp = pk.crop_amplitudes(I, m)
     O = torch.from_numpy(case["init"]).cuda()
     P = torch.from_numpy(case["probe"]).cuda()
     prm = pk.PieParams(batch=900, norm=1, beta=1.0, alpha=1e-3)
     stats = torch.zeros(4, dtype=torch.float64, device="cuda")
     ms = time_calls(torch, lambda: pk.pie_sweep(O, P, scan, amp, prm, stats=stats), sweeps, warmup)
-    return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "positions": 900, "n": 128, "m": 32,
-            "precision": precision, "phi_last": float(stats[0].item())}
+    return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "positions": 900, "n": 128, "m": m,
+            "precision": precision, "method": scan.plan.method, "phi_last": float(stats[0].item())}
 
 
 def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
@@ -303,6 +305,8 @@ def main():
         torch.cuda.empty_cache()
         extra["pie_at_scale_phase1"] = pie_at_scale_rate(torch, pk, "fp32")
         extra["pie_at_scale_phase1_split_bf16"] = pie_at_scale_rate(torch, pk, "split_bf16")
+        extra["pie_at_scale_phase2_fft"] = pie_at_scale_rate(torch, pk, "fp32", m=128)
+        extra["pie_at_scale_phase2_dense"] = pie_at_scale_rate(torch, pk, "fp32", m=128, method="dense")
         extra["pie_tiny_sequential"] = pie_tiny_rate(torch, pk, 1, 0)
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])

@@ -59,6 +59,19 @@ typedef enum {
   PFTPIE_SPLIT_FP16 = 2
 } pftpie_precision;
 
+/* How a plan computes its transform.  DENSE: the contraction F_m psi F_m^T
+ * on matrix cores, in the plan's precision.  FFT: for the full window
+ * m = n in {16, 32, 64, 128} only (the second, full-resolution phase of the
+ * hybrid method, Algorithm 3, Sec. 3.2), a fast 2-D transform held in LDS,
+ * in FP32 whatever the plan's precision; results are the same transform
+ * (centred window order) to float rounding.  AUTO: FFT where it applies,
+ * otherwise DENSE. */
+typedef enum {
+  PFTPIE_METHOD_AUTO = 0,
+  PFTPIE_METHOD_DENSE = 1,
+  PFTPIE_METHOD_FFT = 2
+} pftpie_method;
+
 typedef struct pftpie_plan_s* pftpie_plan;
 typedef struct pie_scan_s* pie_scan;
 
@@ -77,6 +90,15 @@ const char* pftpie_last_error(void);
  *   current device; synchronous.  *out is NULL on failure. */
 pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec,
                                  pftpie_plan* out);
+/* As pftpie_plan_create with an explicit method (pftpie_plan_create uses
+ * AUTO).  FFT for sizes it does not cover returns PFTPIE_E_UNSUPPORTED; an
+ * unknown method value returns PFTPIE_E_INVALID.  The method applies to
+ * pft2d_forward / pft2d_adjoint and to pie_sweep over scans of this plan;
+ * uneven batches (pftpie_group_*) always use the dense contraction. */
+pftpie_status pftpie_plan_create_method(int32_t n, int32_t m, pftpie_precision prec,
+                                        pftpie_method method, pftpie_plan* out);
+/* The method a plan resolved to (DENSE or FFT). */
+pftpie_status pftpie_plan_method(pftpie_plan plan, pftpie_method* method);
 pftpie_status pftpie_plan_destroy(pftpie_plan plan);
 /* Query a plan's sizes and precision (any output pointer may be NULL). */
 pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,
@@ -91,7 +113,8 @@ pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,
  * NULL) receives the best forward + adjoint time per call in milliseconds.
  * The environment variable PFTPIE_TUNE_CACHE names a text file in which
  * results are looked up and recorded (keyed by device name, n, m and
- * precision). */
+ * precision).  The candidates are those of the dense contraction (which
+ * uneven batches use for every plan); best_ms times the dense form. */
 pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* best_ms);
 
 /* Forward: y_b = F_m psi_b F_m^T for b < batch.

@@ -23,6 +23,7 @@ sz = ctypes.c_size_t
 STATUS = {0: "PFTPIE_OK", 1: "PFTPIE_E_INVALID", 2: "PFTPIE_E_UNSUPPORTED",
           3: "PFTPIE_E_NOMEM", 4: "PFTPIE_E_DEVICE"}
 PRECISION = {"fp32": 0, "split_bf16": 1, "split_fp16": 2}
+METHOD = {"auto": 0, "dense": 1, "fft": 2}
 
 
 class PieParams(ctypes.Structure):
@@ -38,6 +39,8 @@ SIGNATURES = {
     "pftpie_status_string": (ctypes.c_char_p, [i32]),
     "pftpie_last_error": (ctypes.c_char_p, []),
     "pftpie_plan_create": (i32, [i32, i32, i32, ctypes.POINTER(c_plan)]),
+    "pftpie_plan_create_method": (i32, [i32, i32, i32, i32, ctypes.POINTER(c_plan)]),
+    "pftpie_plan_method": (i32, [c_plan, ctypes.POINTER(i32)]),
     "pftpie_plan_destroy": (i32, [c_plan]),
     "pftpie_plan_info": (i32, [c_plan, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
     "pftpie_plan_autotune": (i32, [c_plan, i64, ctypes.POINTER(ctypes.c_double)]),

@@ -44,6 +44,8 @@ struct pftpie_plan_s {
   int adj_k1;        // FP32 adjoint: row tiles per stage-2 step (2 or 4)
   int adj_threads;   // FP32 persistent adjoint: threads per workgroup (512 or 768)
   int adj_patch;     // split adjoint: whole patch per wave when m <= 64 (else tile per wave)
+  int method;        // PFTPIE_METHOD_DENSE or PFTPIE_METHOD_FFT (resolved)
+  void* fft_tw;      // device W_n^k, k < n (float2), fast-transform plans only
   int num_cu;        // compute units of the plan's device
   int device;
   void* fa;          // device FA table (float4 blocks, or split 16-bit blocks)
@@ -62,5 +64,11 @@ hipError_t launch_forward(const pftpie_plan_s* p, const float2* psi, float2* y, 
                           hipStream_t st);
 hipError_t launch_adjoint(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch,
                           hipStream_t st);
+// Full-window fast transform (kernels_fft.hip): n = m in {16, 32, 64, 128}.
+bool fft_supported(int n, int m);
+hipError_t launch_fft_forward(const pftpie_plan_s* p, const float2* psi, float2* y, int64_t batch,
+                              hipStream_t st);
+hipError_t launch_fft_adjoint(const pftpie_plan_s* p, const float2* y, float2* psi, int64_t batch,
+                              hipStream_t st);
 
 }  // namespace pftpie

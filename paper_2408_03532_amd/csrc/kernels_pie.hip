@@ -540,18 +540,23 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   const int pblocks = pie_probe_blocks(a.n);
   for (int c0 = 0; c0 < a.J; c0 += batch) {
     const int cnt = (a.J - c0 < batch) ? a.J - c0 : batch;
-    switch (a.mt) {
-      case 1: chunk_mt<1>(a, c0, cnt, st); break;
-      case 2: chunk_mt<2>(a, c0, cnt, st); break;
-      case 3: chunk_mt<3>(a, c0, cnt, st); break;
-      case 4: chunk_mt<4>(a, c0, cnt, st); break;
-      case 5: chunk_mt<5>(a, c0, cnt, st); break;
-      case 6: chunk_mt<6>(a, c0, cnt, st); break;
-      case 7: chunk_mt<7>(a, c0, cnt, st); break;
-      case 8: chunk_mt<8>(a, c0, cnt, st); break;
-      default: return hipErrorInvalidValue;
+    if (a.fft_tw) {
+      const hipError_t e = launch_pie_fft_chunk(a, c0, cnt, st);
+      if (e != hipSuccess) return e;
+    } else {
+      switch (a.mt) {
+        case 1: chunk_mt<1>(a, c0, cnt, st); break;
+        case 2: chunk_mt<2>(a, c0, cnt, st); break;
+        case 3: chunk_mt<3>(a, c0, cnt, st); break;
+        case 4: chunk_mt<4>(a, c0, cnt, st); break;
+        case 5: chunk_mt<5>(a, c0, cnt, st); break;
+        case 6: chunk_mt<6>(a, c0, cnt, st); break;
+        case 7: chunk_mt<7>(a, c0, cnt, st); break;
+        case 8: chunk_mt<8>(a, c0, cnt, st); break;
+        default: return hipErrorInvalidValue;
+      }
     }
-    if (cnt == 1) continue;  // updated in place by the adjoint
+    if (cnt == 1) continue;  // updated in place
     if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt);
     hipLaunchKernelGGL(k_pie_object_gather, dim3(ntiles), dim3(256), 0, st, a, c0, cnt);
     if (a.norm) hipLaunchKernelGGL(k_pie_reduce_max, dim3(1), dim3(1024), 0, st, a, a.probe_step ? pblocks : 0);

@@ -26,6 +26,7 @@ struct PieArgs {
   const int32_t* tile_pos;
   const void* fa;
   const void* ft;
+  const float2* fft_tw;  // full-window fast transform twiddles (null: dense contraction)
   int prec;
   float inv_n2;
   // parameters
@@ -57,6 +58,7 @@ constexpr int kStatBlocks = 512;
 
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);
+hipError_t launch_pie_fft_chunk(const PieArgs& a, int c0, int cnt, hipStream_t st);
 int pie_probe_blocks(int n);
 
 #ifdef __HIPCC__

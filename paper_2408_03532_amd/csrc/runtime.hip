@@ -69,13 +69,23 @@ const char* pftpie_status_string(pftpie_status s) {
 const char* pftpie_last_error(void) { return g_last_error.c_str(); }
 
 pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pftpie_plan* out) {
+  return pftpie_plan_create_method(n, m, prec, PFTPIE_METHOD_AUTO, out);
+}
+
+pftpie_status pftpie_plan_create_method(int32_t n, int32_t m, pftpie_precision prec, pftpie_method method,
+                                        pftpie_plan* out) {
   if (!out) return fail(PFTPIE_E_INVALID, "plan_create: out is NULL");
   *out = nullptr;
+  if (method != PFTPIE_METHOD_AUTO && method != PFTPIE_METHOD_DENSE && method != PFTPIE_METHOD_FFT)
+    return fail(PFTPIE_E_INVALID, "plan_create: unknown method");
   if (n < 1 || n > kMaxN) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= n <= 4096");
   if (m < 1 || m > n) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= m <= n");
   if (prec != PFTPIE_FP32 && prec != PFTPIE_SPLIT_BF16 && prec != PFTPIE_SPLIT_FP16)
     return fail(PFTPIE_E_INVALID, "plan_create: unknown precision");
   if (m > kMaxM) return fail(PFTPIE_E_UNSUPPORTED, "plan_create: m > 128 is not supported");
+  if (method == PFTPIE_METHOD_FFT && !fft_supported(n, m))
+    return fail(PFTPIE_E_UNSUPPORTED, "plan_create: the fast transform needs m = n in {16, 32, 64, 128}");
+  const bool use_fft = method == PFTPIE_METHOD_FFT || (method == PFTPIE_METHOD_AUTO && fft_supported(n, m));
   pftpie_plan_s* p = new (std::nothrow) pftpie_plan_s();
   if (!p) return fail(PFTPIE_E_NOMEM, "plan_create: host allocation failed");
   p->n = n;
@@ -84,6 +94,8 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
   p->nb = ceil16(n);
   p->mt = ceil16(m);
   p->fa_ctiles = fa_ctiles_for(p->mt);
+  p->method = use_fft ? PFTPIE_METHOD_FFT : PFTPIE_METHOD_DENSE;
+  p->fft_tw = nullptr;
   p->fwd_ct = prec == PFTPIE_FP32 ? fwd_ct_default(p->mt) : fwd_ct_default_split(p->mt);
   p->use_lds = 1;
   p->use_lds_adj = 1;
@@ -137,6 +149,19 @@ pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pf
     delete p;
     return hip_fail(e, "plan_create: upload");
   }
+  if (use_fft) {
+    std::vector<float> tw;
+    build_fft_twiddles(n, tw);
+    e = hipMalloc((void**)&p->fft_tw, tw.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(p->fft_tw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p->fa);
+      (void)hipFree(p->ft);
+      (void)hipFree(p->fft_tw);
+      delete p;
+      return hip_fail(e, "plan_create: fast-transform twiddles");
+    }
+  }
   *out = p;
   return PFTPIE_OK;
 }
@@ -145,7 +170,15 @@ pftpie_status pftpie_plan_destroy(pftpie_plan plan) {
   if (!plan) return PFTPIE_OK;
   (void)hipFree(plan->fa);
   (void)hipFree(plan->ft);
+  if (plan->fft_tw) (void)hipFree(plan->fft_tw);
   delete plan;
+  return PFTPIE_OK;
+}
+
+pftpie_status pftpie_plan_method(pftpie_plan plan, pftpie_method* method) {
+  if (pftpie_status s = check_plan(plan)) return s;
+  if (!method) return fail(PFTPIE_E_INVALID, "plan_method: method is NULL");
+  *method = (pftpie_method)plan->method;
   return PFTPIE_OK;
 }
 
@@ -162,8 +195,11 @@ pftpie_status pft2d_forward(pftpie_plan plan, const void* psi, void* y, int64_t 
   if (pftpie_status s = check_batch_io(plan, psi, (size_t)plan->n * plan->n, y, (size_t)plan->m * plan->m,
                                        batch, "pft2d_forward"))
     return s;
-  hipError_t e = launch_forward(plan, static_cast<const float2*>(psi), static_cast<float2*>(y), batch,
-                                static_cast<hipStream_t>(stream));
+  const float2* in = static_cast<const float2*>(psi);
+  float2* out = static_cast<float2*>(y);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = plan->method == PFTPIE_METHOD_FFT ? launch_fft_forward(plan, in, out, batch, st)
+                                                   : launch_forward(plan, in, out, batch, st);
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pft2d_forward: launch");
 }
 
@@ -172,8 +208,11 @@ pftpie_status pft2d_adjoint(pftpie_plan plan, const void* y, void* psi, int64_t 
   if (pftpie_status s = check_batch_io(plan, y, (size_t)plan->m * plan->m, psi, (size_t)plan->n * plan->n,
                                        batch, "pft2d_adjoint"))
     return s;
-  hipError_t e = launch_adjoint(plan, static_cast<const float2*>(y), static_cast<float2*>(psi), batch,
-                                static_cast<hipStream_t>(stream));
+  const float2* in = static_cast<const float2*>(y);
+  float2* out = static_cast<float2*>(psi);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = plan->method == PFTPIE_METHOD_FFT ? launch_fft_adjoint(plan, in, out, batch, st)
+                                                   : launch_adjoint(plan, in, out, batch, st);
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pft2d_adjoint: launch");
 }
 

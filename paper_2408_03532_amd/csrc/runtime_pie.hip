@@ -220,6 +220,7 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.tile_pos = scan->tile_pos;
   a.fa = pl->fa;
   a.ft = pl->ft;
+  a.fft_tw = pl->method == PFTPIE_METHOD_FFT ? static_cast<const float2*>(pl->fft_tw) : nullptr;
   a.prec = pl->prec;
   a.inv_n2 = (float)(1.0 / ((double)pl->n * pl->n));
   a.norm = p->norm;

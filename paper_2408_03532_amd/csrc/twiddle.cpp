@@ -59,6 +59,15 @@ void build_twiddle_tables(int n, int m, int fa_ctiles, std::vector<float>& fa, s
       });
 }
 
+void build_fft_twiddles(int n, std::vector<float>& tw) {
+  tw.assign((size_t)2 * n, 0.f);
+  for (int k = 0; k < n; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)n;
+    tw[2 * k] = (float)std::cos(ang);
+    tw[2 * k + 1] = (float)-std::sin(ang);
+  }
+}
+
 uint16_t f32_to_bf16_rne(float x) {
   uint32_t u;
   std::memcpy(&u, &x, 4);

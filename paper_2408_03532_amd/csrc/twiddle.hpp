@@ -20,6 +20,10 @@ void build_twiddle_tables(int n, int m, int fa_ctiles, std::vector<float>& fa, s
 void build_split_tables(int n, int m, int fa_ctiles, int kind, std::vector<uint16_t>& fa,
                         std::vector<uint16_t>& ft);
 
+// Twiddles of the full-window fast transform: tw[2k], tw[2k+1] = re, im of
+// exp(-2 pi i k / n), k < n, computed in double and rounded once.
+void build_fft_twiddles(int n, std::vector<float>& tw);
+
 // Round-to-nearest-even conversions used by the split tables.
 uint16_t f32_to_bf16_rne(float x);
 float bf16_to_f32(uint16_t h);

@@ -34,18 +34,28 @@ def _require(t, name, dtype=torch.complex64):
 
 
 class Plan:
-    """Twiddle tables of one (n, m, precision) on one device."""
+    """Twiddle tables of one (n, m, precision) on one device.
 
-    def __init__(self, n, m, precision="fp32", device=None):
+    method: "auto" (the fast full-window transform when m = n in
+    {16, 32, 64, 128}, else the dense contraction), "dense" or "fft"; the
+    resolved choice is in ``self.method``."""
+
+    def __init__(self, n, m, precision="fp32", device=None, method="auto"):
         if precision not in _lib.PRECISION:
             raise ValueError(f"precision must be one of {sorted(_lib.PRECISION)}")
+        if method not in _lib.METHOD:
+            raise ValueError(f"method must be one of {sorted(_lib.METHOD)}")
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else
                            torch.device(device).index or 0)
         self.n, self.m, self.precision, self.device = int(n), int(m), precision, dev
         h = _lib.c_plan()
         with torch.cuda.device(dev):
-            _lib.call("pftpie_plan_create", n, m, _lib.PRECISION[precision], ctypes.byref(h))
+            _lib.call("pftpie_plan_create_method", n, m, _lib.PRECISION[precision], _lib.METHOD[method],
+                      ctypes.byref(h))
         self.handle = h
+        resolved = ctypes.c_int32()
+        _lib.call("pftpie_plan_method", self.handle, ctypes.byref(resolved))
+        self.method = {v: k for k, v in _lib.METHOD.items()}[resolved.value]
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -91,26 +101,26 @@ class Plan:
         return out
 
 
-def get_plan(n, m, precision="fp32", device=None):
-    """Cached plan for (device, n, m, precision)."""
+def get_plan(n, m, precision="fp32", device=None, method="auto"):
+    """Cached plan for (device, n, m, precision, method)."""
     dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
-    key = (dev, int(n), int(m), precision)
+    key = (dev, int(n), int(m), precision, method)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
-            p = Plan(n, m, precision, device=torch.device("cuda", dev))
+            p = Plan(n, m, precision, device=torch.device("cuda", dev), method=method)
             _plans[key] = p
         return p
 
 
-def pft2d_forward(psi, m, precision="fp32", out=None):
+def pft2d_forward(psi, m, precision="fp32", out=None, method="auto"):
     """Centred m x m partial DFT of every trailing n x n patch of psi."""
-    return get_plan(psi.shape[-1], m, precision, psi.device).forward(psi.contiguous(), out)
+    return get_plan(psi.shape[-1], m, precision, psi.device, method).forward(psi.contiguous(), out)
 
 
-def pft2d_adjoint(y, n, precision="fp32", out=None):
+def pft2d_adjoint(y, n, precision="fp32", out=None, method="auto"):
     """Adjoint F_m^H y conj(F_m) of every trailing m x m block of y."""
-    return get_plan(n, y.shape[-1], precision, y.device).adjoint(y.contiguous(), out)
+    return get_plan(n, y.shape[-1], precision, y.device, method).adjoint(y.contiguous(), out)
 
 
 class _PFT2D(torch.autograd.Function):

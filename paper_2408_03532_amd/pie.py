@@ -34,16 +34,17 @@ class PieParams:
 
 class Scan:
     """Scan positions (top-left (row, col) of each n x n window) inside an
-    H x W object, bound to the plan of (n, m, precision)."""
+    H x W object, bound to the plan of (n, m, precision, method); see
+    ``pft.Plan`` for the method."""
 
-    def __init__(self, pos, obj_shape, n, m, precision="fp32", device=None):
+    def __init__(self, pos, obj_shape, n, m, precision="fp32", device=None, method="auto"):
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
         if pos.ndim != 2 or pos.shape[1] != 2:
             raise ValueError("pos must be [J][2]")
         self.pos = pos
         self.J = pos.shape[0]
         self.H, self.W = (int(v) for v in obj_shape)
-        self.plan = get_plan(n, m, precision, device)
+        self.plan = get_plan(n, m, precision, device, method)
         self.n, self.m, self.precision = self.plan.n, self.plan.m, precision
         h = _lib.c_scan()
         with torch.cuda.device(self.plan.device):
@@ -127,7 +128,8 @@ def rel_change(stats_host):
 
 
 def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_full=100,
-               tol_full=5e-4, params=None, full_params=None, order=None, callback=None):
+               tol_full=5e-4, params=None, full_params=None, order=None, callback=None,
+               precision="fp32", full_method="auto"):
     """Hybrid PIE of Algorithm 3 (Sec. 3.2), on the device.
 
     Phase 1 runs partial-transform sweeps on the central m x m window of the
@@ -135,6 +137,8 @@ def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_
     phase 2 starts from that object and runs full-window sweeps (m = n) on
     the full data until tol_full or iters_full.  obj / probe are updated in
     place; intensity is a device float32 [J][n][n] fftshift-layout tensor.
+    Phase 2 uses the fast full-window transform where it applies
+    (full_method "auto"; "dense" forces the contraction at m = n).
     Returns the history [(phase, sweep, Phi, rel_change)].  The only host
     synchronisation is the read-back of the 4 statistics per sweep.
     """
@@ -145,7 +149,8 @@ def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_
     raise_nonfinite = True
     for phase, (mm, iters, tol, prm) in enumerate(((m, iters_pft, tol_pft, params),
                                                     (n, iters_full, tol_full, full_params))):
-        scan = Scan(pos, obj.shape, n, mm, device=obj.device)
+        scan = Scan(pos, obj.shape, n, mm, precision=precision, device=obj.device,
+                    method=full_method if phase == 1 else "auto")
         amp = crop_amplitudes(intensity, mm)
         stats = torch.zeros(4, dtype=torch.float64, device=obj.device)
         for it in range(iters):

@@ -52,6 +52,27 @@ def test_plan_create_large_window_is_unsupported():
     assert L.pftpie_plan_create(512, 256, 0, ctypes.byref(h)) == 2
 
 
+@pytest.mark.parametrize("n,m,method,status,msg", [
+    (32, 32, 7, 1, b"unknown method"),
+    (64, 32, 2, 2, b"m = n in {16, 32, 64, 128}"),   # the fast transform needs the full window
+    (256, 256, 2, 2, b"m > 128"),                    # windows above 128 are not built
+    (48, 48, 2, 2, b"m = n in {16, 32, 64, 128}"),   # not a supported length
+])
+def test_plan_method_rejected_on_the_host(n, m, method, status, msg):
+    L = pk.lib()
+    h = ctypes.c_void_p(123)
+    assert L.pftpie_plan_create_method(n, m, 0, method, ctypes.byref(h)) == status
+    assert h.value is None
+    assert msg in L.pftpie_last_error()
+
+
+def test_plan_method_query_needs_a_plan():
+    L = pk.lib()
+    out = ctypes.c_int32(-1)
+    assert L.pftpie_plan_method(None, ctypes.byref(out)) == 1
+    assert out.value == -1
+
+
 def test_null_handles_are_invalid_not_fatal():
     L = pk.lib()
     assert L.pft2d_forward(None, None, None, 1, None) == 1
