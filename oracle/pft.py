@@ -33,49 +33,77 @@ def window(m):
     return np.arange(m, dtype=np.int64) - (m // 2)
 
 
-def twiddles(n, m):
-    """Partial DFT matrix F_m[c, k] = exp(-2 pi i t_c k / n), shape [m][n].
+def twiddles(n, m, period=None):
+    """Partial DFT matrix F_m[c, k] = exp(-2 pi i t_c k / N), shape [m][n],
+    with DFT length N = ``period`` (default n).
 
     The DFT kernel of Sec. 3.1.1, eq. (7), restricted to the kept rows t_c.
-    The phase t_c*k is reduced modulo n in integer arithmetic before the
-    trigonometric call, so the argument stays in [0, 2 pi).
+    A period N > n is the masked full field of the paper's experiments
+    (Sec. 4.2: an n x n illuminated window inside an N x N field, every
+    other pixel zero): the field's DFT at frequency t only sums the window's
+    pixels, k = 0..n-1 counted from the window's corner.  The phase t_c*k is
+    reduced modulo N in integer arithmetic before the trigonometric call, so
+    the argument stays in [0, 2 pi).
     """
-    if not (1 <= m <= n):
-        raise ValueError("need 1 <= m <= n")
+    N = n if period is None else int(period)
+    if not (1 <= n <= N and 1 <= m <= N):
+        raise ValueError("need 1 <= n <= period and 1 <= m <= period")
     t = window(m)
     k = np.arange(n, dtype=np.int64)
-    phase_int = np.mod(np.outer(t, k), n)          # exact integer reduction
-    return np.exp(-2j * np.pi * phase_int.astype(np.float64) / n)
+    phase_int = np.mod(np.outer(t, k), N)          # exact integer reduction
+    return np.exp(-2j * np.pi * phase_int.astype(np.float64) / N)
 
 
-def forward(psi, m):
+def shift_ramp(m, shift, period):
+    """Phase of the window's position in the field: R[c1, c2] =
+    exp(-2 pi i (t_c1 s1 + t_c2 s2) / N) for a window whose corner sits at
+    field pixel (s1, s2) (the DFT shift theorem), reduced modulo N."""
+    t = window(m)
+    s1, s2 = (int(v) for v in shift)
+    r1 = np.exp(-2j * np.pi * np.mod(t * s1, period).astype(np.float64) / period)
+    r2 = np.exp(-2j * np.pi * np.mod(t * s2, period).astype(np.float64) / period)
+    return np.outer(r1, r2)
+
+
+def forward(psi, m, period=None, shift=None):
     """Y = F_m psi F_m^T for each trailing [n][n] slice (Appendix A, eq. (16)).
 
     psi: array [..., n, n] (any complex/real dtype; upcast to complex128).
     Returns complex128 [..., m, m]:
-        Y[c1, c2] = sum_{k1,k2} psi[k1,k2] exp(-2 pi i (t_c1 k1 + t_c2 k2)/n).
+        Y[c1, c2] = sum_{k1,k2} psi[k1,k2] exp(-2 pi i (t_c1 k1 + t_c2 k2)/N).
     The 2-D sum factorises into one DFT per axis, so it is two matrix
-    products with the same partial DFT matrix.
+    products with the same partial DFT matrix.  With a period N > n and the
+    window's corner ``shift`` = (s1, s2) in the N x N field, Y is further
+    multiplied by ``shift_ramp``: the kept coefficients of the whole masked
+    field.
     """
     psi = np.asarray(psi).astype(np.complex128)
     n = psi.shape[-1]
     if psi.shape[-2] != n:
         raise ValueError("patches must be square")
-    F = twiddles(n, m)
-    return F @ psi @ F.T
+    N = n if period is None else int(period)
+    F = twiddles(n, m, N)
+    y = F @ psi @ F.T
+    if shift is not None:
+        y = y * shift_ramp(m, shift, N)
+    return y
 
 
-def adjoint(y, n):
+def adjoint(y, n, period=None, shift=None):
     """X = F_m^H Y conj(F_m): the adjoint of ``forward`` (no normalisation).
 
     y: array [..., m, m].  Returns complex128 [..., n, n]:
-        X[k1, k2] = sum_{c1,c2} Y[c1,c2] exp(+2 pi i (t_c1 k1 + t_c2 k2)/n).
+        X[k1, k2] = sum_{c1,c2} Y[c1,c2] exp(+2 pi i (t_c1 k1 + t_c2 k2)/N),
+    after multiplying Y by the conjugate ``shift_ramp`` when a shift is given.
     """
     y = np.asarray(y).astype(np.complex128)
     m = y.shape[-1]
     if y.shape[-2] != m:
         raise ValueError("coefficient blocks must be square")
-    F = twiddles(n, m)
+    N = n if period is None else int(period)
+    if shift is not None:
+        y = y * np.conj(shift_ramp(m, shift, N))
+    F = twiddles(n, m, N)
     return F.conj().T @ y @ F.conj()
 
 

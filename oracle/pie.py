@@ -62,7 +62,7 @@ def amplitudes(intensity, m):
 
 
 def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
-              beta=1.0, gamma=0.0, alpha=1e-3):
+              beta=1.0, gamma=0.0, alpha=1e-3, period=None):
     """One PIE / ePIE iteration (Sec. 2.1, eqs. (5)-(6)) over all positions.
 
     obj   [H][W] complex, probe [n][n] complex, pos [J][2] integer top-left
@@ -75,6 +75,16 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
               pseudo-inverse equals sum_j ||(|u_j| - a_j)||^2 / (J n^2);
       dO    = object after minus object before the sweep;
       n_nonfinite counts non-finite entries of the new object (and probe).
+
+    period: the masked-field form of the experiments (Sec. 4.2): the object
+    is the whole N x N field (N = period), exit wave j is the field masked
+    to the n x n window at pos[j] (times the probe), its data are the kept
+    coefficients of the field's N-point DFT (``pft.forward`` with period N
+    and the window's shift ramp), and the correction is the inverse N-point
+    DFT of the coefficient change restricted to the window, i.e.
+    F_m^H (...) conj(F_m) / N^2 with the conjugate ramp; phi is normalised
+    by J N^2.  The ramp is applied literally here even though it cancels
+    (the projection keeps it, the adjoint removes it).
     """
     O = np.asarray(obj).astype(np.complex128).copy()
     P = np.asarray(probe).astype(np.complex128).copy()
@@ -82,6 +92,7 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
     amp = np.asarray(amp).astype(np.float64)
     n = P.shape[0]
     J = pos.shape[0]
+    N = n if period is None else int(period)
     order = np.arange(J) if order is None else np.asarray(order, dtype=np.int64)
     O_start = O.copy()
     phi_acc = 0.0
@@ -95,10 +106,11 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
             r, c = pos[j]
             Oj = O[r:r + n, c:c + n]
             psi = P * Oj                                   # exit wave, eq. (1)
-            u = pft.forward(psi, m)
+            shift = None if period is None else (r, c)
+            u = pft.forward(psi, m, N, shift)
             up = project(u, amp[j])
             phi_acc += float(np.sum((np.abs(u) - amp[j]) ** 2))
-            delta = pft.adjoint(up - u, n) / float(n * n)  # P_M(psi) - psi
+            delta = pft.adjoint(up - u, n, N, shift) / float(N * N)  # P_M(psi) - psi
             numO[r:r + n, c:c + n] += np.conj(P) * delta
             D[r:r + n, c:c + n] += np.abs(P) ** 2
             if gamma > 0.0:
@@ -112,7 +124,7 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
             O = O + beta * numO / (D + alpha * D.max())
             if gamma > 0.0:
                 P = P + gamma * numP / (E + alpha * E.max())
-    phi = phi_acc / (J * n * n)
+    phi = phi_acc / (J * N * N)
     dO2 = float(np.sum(np.abs(O - O_start) ** 2))
     O2 = float(np.sum(np.abs(O_start) ** 2))
     nonfinite = int(np.count_nonzero(~np.isfinite(O)))

@@ -193,3 +193,44 @@ def test_plausible_mistakes_are_caught():
     assert rel(F.conj() @ psi @ F.conj().T, ref) > 0.5  # wrong sign
     Fo = np.exp(-2j * np.pi * np.outer(np.arange(m) - m // 2 + 1, np.arange(n)) / n)
     assert rel(Fo @ psi @ Fo.T, ref) > 0.5          # window off by one
+
+
+# --- masked full field: DFT period larger than the window (Sec. 4.2) -------
+
+@pytest.mark.parametrize("n,N,m,shift", [(8, 24, 10, (5, 11)), (6, 16, 7, (0, 9)), (12, 12, 5, (0, 0))])
+def test_period_forward_equals_crop_of_zero_padded_field_fft(n, N, m, shift):
+    # the window sits at `shift` in an N x N field of zeros; the kept
+    # coefficients are the centred m x m crop of the field's fftshift-ed DFT
+    rng = np.random.default_rng(41)
+    psi = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    field = np.zeros((N, N), dtype=np.complex128)
+    s1, s2 = shift
+    field[s1:s1 + n, s2:s2 + n] = psi
+    spec = np.fft.fftshift(np.fft.fft2(field))
+    lo = N // 2 - m // 2
+    ref = spec[lo:lo + m, lo:lo + m]
+    got = pft.forward(psi, m, period=N, shift=shift)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_period_equal_to_window_and_no_shift_is_the_plain_transform():
+    rng = np.random.default_rng(42)
+    psi = rng.standard_normal((3, 16, 16)) + 1j * rng.standard_normal((3, 16, 16))
+    assert np.array_equal(pft.forward(psi, 6, period=16), pft.forward(psi, 6))
+    y = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+    assert np.array_equal(pft.adjoint(y, 16, period=16), pft.adjoint(y, 16))
+
+
+def test_period_adjoint_identity_with_shift():
+    rng = np.random.default_rng(43)
+    n, N, m, shift = 10, 32, 9, (7, 20)
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    y = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    lhs = np.vdot(pft.forward(x, m, N, shift), y)
+    rhs = np.vdot(x, pft.adjoint(y, n, N, shift))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_period_twiddles_reject_a_window_larger_than_the_period():
+    with pytest.raises(ValueError):
+        pft.twiddles(16, 4, period=8)
