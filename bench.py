@@ -166,6 +166,26 @@ def pie_at_scale_rate(torch, pk, precision, sweeps=10, warmup=2, m=32, method="a
             "precision": precision, "method": scan.plan.method, "phi_last": float(stats[0].item())}
 
 
+def masked_field_rate(torch, pk, precision="fp32", sweeps=5, warmup=1):
+    """Sweeps of the paper-size masked field (16384^2 field, 8192^2 windows,
+    m = 128, 9 positions in one overlap-normalised chunk): 2 x 8 n m (n + m)
+    x 9 = 1.257 TFLOP of partial transforms per sweep."""
+    import workloads
+    case = workloads.masked_field()
+    scan = pk.Scan(case["pos"], case["obj"].shape, 8192, 128, precision=precision, period=case["period"])
+    O = torch.from_numpy(case["init"]).cuda()
+    P = torch.from_numpy(case["probe"]).cuda()
+    A = torch.from_numpy(case["amp"]).cuda()
+    del case
+    prm = pk.PieParams(batch=9, norm=1, beta=1.0, alpha=1e-3)
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ms = time_calls(torch, lambda: pk.pie_sweep(O, P, scan, A, prm, stats=stats), sweeps, warmup)
+    flops = 2 * 8.0 * 8192 * 128 * (8192 + 128) * 9
+    return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "tflops_alg": flops / (ms * 1e-3) / 1e12,
+            "field": 16384, "n": 8192, "m": 128, "positions": 9, "precision": precision,
+            "phi_last": float(stats[0].item())}
+
+
 def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
     import workloads
     case = workloads.tiny_pie()
@@ -307,6 +327,7 @@ def main():
         extra["pie_at_scale_phase1_split_bf16"] = pie_at_scale_rate(torch, pk, "split_bf16")
         extra["pie_at_scale_phase2_fft"] = pie_at_scale_rate(torch, pk, "fp32", m=128)
         extra["pie_at_scale_phase2_dense"] = pie_at_scale_rate(torch, pk, "fp32", m=128, method="dense")
+        extra["pie_masked_field_16384"] = masked_field_rate(torch, pk)
         extra["pie_tiny_sequential"] = pie_tiny_rate(torch, pk, 1, 0)
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])

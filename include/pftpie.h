@@ -83,7 +83,7 @@ const char* pftpie_last_error(void);
  * The exact DFT restricted to the window (Appendix A, 2-D DFT; Sec. 3.1.1,
  * 1-D DFT): the quantity the paper's PFT approximates (Sec. 3.1, Fig. 2).
  *
- * pftpie_plan_create: 1 <= m <= n <= 4096.  Builds the partial DFT matrix
+ * pftpie_plan_create: 1 <= m <= n <= 8192.  Builds the partial DFT matrix
  *   F_m[c][k] = exp(-2 pi i ((t_c k) mod n) / n) in double (integer
  *   reduction of the phase first), rounds it to the plan's precision and
  *   uploads it in the kernels' tile order.  Allocates device memory on the
@@ -99,6 +99,22 @@ pftpie_status pftpie_plan_create_method(int32_t n, int32_t m, pftpie_precision p
                                         pftpie_method method, pftpie_plan* out);
 /* The method a plan resolved to (DENSE or FFT). */
 pftpie_status pftpie_plan_method(pftpie_plan plan, pftpie_method* method);
+/* Masked larger field (Sec. 4.2: an n x n illuminated window inside a
+ * period x period field, every other pixel zero): the plan's transform uses
+ * DFT length `period` (n <= period <= 2^20),
+ *   F_m[c][k] = exp(-2 pi i ((t_c k) mod period) / period),  k < n,
+ * so pft2d_forward returns the kept coefficients of the whole field for a
+ * window at the field's origin.  A window whose corner sits at (s1, s2)
+ * has them times exp(-2 pi i ((t_c1 s1 + t_c2 s2) mod period) / period)
+ * (shift theorem); the caller applies that phase where it needs the
+ * field's coefficients themselves.  pie_sweep and the amplitude loss use
+ * magnitudes only and need no phase (the adjoint of the phase cancels it);
+ * pie_sweep normalises its correction by 1/period^2 (the inverse
+ * period-point DFT of the band change) and Phi by J period^2.  The FFT
+ * method needs period == n.  pftpie_plan_create is period = n. */
+pftpie_status pftpie_plan_create_period(int32_t n, int32_t m, int32_t period, pftpie_precision prec,
+                                        pftpie_method method, pftpie_plan* out);
+pftpie_status pftpie_plan_period(pftpie_plan plan, int32_t* period);
 pftpie_status pftpie_plan_destroy(pftpie_plan plan);
 /* Query a plan's sizes and precision (any output pointer may be NULL). */
 pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,

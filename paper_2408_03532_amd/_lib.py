@@ -41,6 +41,8 @@ SIGNATURES = {
     "pftpie_plan_create": (i32, [i32, i32, i32, ctypes.POINTER(c_plan)]),
     "pftpie_plan_create_method": (i32, [i32, i32, i32, i32, ctypes.POINTER(c_plan)]),
     "pftpie_plan_method": (i32, [c_plan, ctypes.POINTER(i32)]),
+    "pftpie_plan_create_period": (i32, [i32, i32, i32, i32, i32, ctypes.POINTER(c_plan)]),
+    "pftpie_plan_period": (i32, [c_plan, ctypes.POINTER(i32)]),
     "pftpie_plan_destroy": (i32, [c_plan]),
     "pftpie_plan_info": (i32, [c_plan, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
     "pftpie_plan_autotune": (i32, [c_plan, i64, ctypes.POINTER(ctypes.c_double)]),

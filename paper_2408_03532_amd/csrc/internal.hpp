@@ -12,7 +12,8 @@
 
 namespace pftpie {
 
-constexpr int kMaxN = 4096;
+constexpr int kMaxN = 8192;             // window pixels per axis
+constexpr int kMaxPeriod = 1 << 20;     // DFT length (masked larger fields)
 constexpr int kMaxM = 128;  // 8 accumulator tiles per axis
 constexpr size_t kMaxLdsTable = 160 * 1024;  // LDS per compute unit on gfx950
 
@@ -35,6 +36,7 @@ inline int adj_waves(int nb) { return nb >= 4 ? 4 : nb; }
 
 struct pftpie_plan_s {
   int32_t n, m;
+  int32_t period;    // DFT length (n, or the size of a masked larger field)
   pftpie_precision prec;
   int nb, mt;        // ceil(n/16), ceil(m/16)
   int fa_ctiles;     // column tiles allocated in FA (covers every forward split)

@@ -21,6 +21,8 @@
 //   k_pie_reduce_max, k_pie_apply   maxima and the normalised updates.
 // Per sweep: k_pie_begin (object copy, ranks, clears) and the statistics
 // pair k_pie_stats_part / k_pie_stats_final (fixed-order sums).
+#include <type_traits>
+
 #include "internal.hpp"
 #include "pft_split.hpp"
 #include "pie.hpp"
@@ -62,10 +64,35 @@ struct GatherTrackSrc {
   }
 };
 
+// Magnitude projection (eq. (3)) of coefficient (c1, c2) of chunk entry q:
+// stores the residual r = a u/|u| - u (theta(0) = 0; zero for an invalid
+// entry) and returns the objective term (|u| - a)^2 (eq. (4)).
+__device__ __forceinline__ double pie_project_one(const PieArgs& a, int q, int j, bool valid, int c1, int c2,
+                                                  float ur, float ui) {
+  const int m = a.m;
+  const float av = a.amp[(size_t)j * m * m + (size_t)c1 * m + c2];
+  const float mag = sqrtf(ur * ur + ui * ui);
+  float2 r;
+  if (!valid) {
+    r = make_float2(0.f, 0.f);
+  } else if (mag > 0.f) {
+    const float s = av / mag - 1.f;  // a u/|u| - u = (a/|u| - 1) u
+    r = make_float2(s * ur, s * ui);
+  } else {
+    r = make_float2(av - ur, -ui);  // theta(0) = 0
+  }
+  a.R[(size_t)q * m * m + (size_t)c1 * m + c2] = r;
+  const double d = (double)mag - (double)av;
+  return valid ? d * d : 0.0;
+}
+
 // Forward + projection.  Block = WR x WC waves: wave (wr, wc) runs strips
-// wr, wr + WR, ... for column-tile group wc; partial spectra of wr > 0 are
-// added to wr = 0 through LDS, whose waves then apply the projection.
-template <class PR, int MT, int CT, int WR, bool EXACT, bool TRACK>
+// g, g + G, ... (row group g = split * WR + wr, G = WR * splits) for
+// column-tile group wc; partial spectra of wr > 0 are added to wr = 0
+// through LDS, whose waves then apply the projection, or, when the
+// position's strips are split over several workgroups (SPLIT, blockIdx.y),
+// store the workgroup's partial spectrum for k_pie_project.
+template <class PR, int MT, int CT, int WR, bool EXACT, bool TRACK, bool SPLIT, int RS = 1>
 __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(PieArgs a, int c0) {
   constexpr int WC = (MT + CT - 1) / CT;
   const int q = blockIdx.x;
@@ -76,10 +103,12 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
   const int c2t0 = wc * CT;
   const int2 ps = a.pos[j];
   const int lane = lane_id();
+  const int g0 = SPLIT ? (int)blockIdx.y * WR + wr : wr;
+  const int G = SPLIT ? (int)gridDim.y * WR : WR;
   f32x4 Yre[MT][CT], Yim[MT][CT];
   if constexpr (TRACK) {
     GatherTrackSrc<EXACT> src{{a.O, a.P, a.W, a.n, ps.x, ps.y}, 0.f, 0.f};
-    fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, wr, WR);
+    fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, g0, G);
     if (wc == 0) {
       const float mp = wave_max(src.mp), mo = wave_max(src.mo);
       if (lane == 0 && valid) {
@@ -89,7 +118,10 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
     }
   } else {
     GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
-    fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, wr, WR);
+    if constexpr (RS > 1)
+      fwd_wave_rs<MT, CT, RS>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, g0, G);
+    else
+      fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, g0, G);
   }
   if constexpr (WR > 1) {
     // partial spectra: [WR - 1][WC][MT * CT * 2][64 lanes] f32x4
@@ -119,8 +151,19 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
     }
   }
   const int m = a.m;
-  const float* amp = a.amp + (size_t)j * m * m;
-  float2* res = a.R + (size_t)q * m * m;
+  if constexpr (SPLIT) {
+    float2* part = a.part + ((size_t)q * gridDim.y + blockIdx.y) * m * m;
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int2 rc = tile_rc<Orient<PR>::TR>(c1t, c2t0 + ct, i, lane);
+          if (rc.x < m && rc.y < m) part[(size_t)rc.x * m + rc.y] = make_float2(Yre[c1t][ct][i], Yim[c1t][ct][i]);
+        }
+    return;
+  }
   double phi = 0.0;
 #pragma unroll
   for (int c1t = 0; c1t < MT; ++c1t)
@@ -129,28 +172,39 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int2 rc = tile_rc<Orient<PR>::TR>(c1t, c2t0 + ct, i, lane);
-        const int c1 = rc.x, c2 = rc.y;
-        if (c1 < m && c2 < m) {
-          const float ur = Yre[c1t][ct][i], ui = Yim[c1t][ct][i];
-          const float av = amp[(size_t)c1 * m + c2];
-          const float mag = sqrtf(ur * ur + ui * ui);
-          float2 r;
-          if (!valid) {
-            r = make_float2(0.f, 0.f);
-          } else if (mag > 0.f) {
-            const float s = av / mag - 1.f;  // a u/|u| - u = (a/|u| - 1) u
-            r = make_float2(s * ur, s * ui);
-          } else {
-            r = make_float2(av - ur, -ui);  // theta(0) = 0
-          }
-          res[(size_t)c1 * m + c2] = r;
-          const double d = (double)mag - (double)av;
-          phi += valid ? d * d : 0.0;
-        }
+        if (rc.x < m && rc.y < m) phi += pie_project_one(a, q, j, valid, rc.x, rc.y, Yre[c1t][ct][i], Yim[c1t][ct][i]);
       }
     }
   phi = wave_sum(phi);
   if (lane == 0 && valid) a.phi_part[(size_t)j * 4 + wc] = phi;
+}
+
+// Sum of the partial spectra of chunk entry q (fixed order over the splits)
+// and the projection; blockIdx.y takes a quarter of the rows, its objective
+// sum goes to that position's slot blockIdx.y.
+__global__ __launch_bounds__(256) void k_pie_project(PieArgs a, int c0) {
+  __shared__ double sh[4];
+  const int q = blockIdx.x;
+  bool valid;
+  const int j = pos_index(a.order, a.J, c0, q, &valid);
+  const int m = a.m, S = a.splits;
+  const int rows = (m + 3) / 4, r0 = blockIdx.y * rows;
+  const int r1 = r0 + rows < m ? r0 + rows : m;
+  const float2* part = a.part + (size_t)q * S * m * m;
+  double phi = 0.0;
+  for (int t = r0 * m + threadIdx.x; t < r1 * m; t += blockDim.x) {
+    float ur = 0.f, ui = 0.f;
+    for (int s = 0; s < S; ++s) {
+      const float2 v = part[(size_t)s * m * m + t];
+      ur += v.x;
+      ui += v.y;
+    }
+    phi += pie_project_one(a, q, j, valid, t / m, t % m, ur, ui);
+  }
+  phi = wave_sum(phi);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = phi;
+  __syncthreads();
+  if (threadIdx.x == 0 && valid) a.phi_part[(size_t)j * 4 + blockIdx.y] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Residual source of the adjoint (m x m, masked).
@@ -246,10 +300,10 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
     }
     UpdateSink sink{a.O, a.P, a.n, a.W, ps.x, ps.y, a.norm, a.probe_step, (int)valid,
                     a.inv_n2, a.beta, a.gamma, regP, regO};
-    for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+    for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
   } else {
     DeltaSink sink{a.dpsi + (size_t)q * a.n * a.n, a.n, a.inv_n2};
-    for (int kt2 = w; kt2 < a.nb; kt2 += nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+    for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
   }
 }
 
@@ -454,7 +508,7 @@ __global__ __launch_bounds__(64) void k_pie_stats_final(PieArgs a, int nblocks) 
     for (int c = 0; c < 3; ++c) v[c + 1] += a.red[(size_t)b * 3 + c];
   for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
   if (threadIdx.x == 0) {
-    a.stats[0] = v[0] / ((double)a.J * a.n * a.n);
+    a.stats[0] = v[0] / ((double)a.J * a.period * a.period);
     a.stats[1] = v[1];
     a.stats[2] = v[2];
     a.stats[3] = v[3];
@@ -495,11 +549,27 @@ static void fwd_launch(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   constexpr int CT = (MT <= 2) ? MT : 2;
   constexpr int WC = (MT + CT - 1) / CT;
   constexpr int WR = pie_wr<MT>();
-  dim3 grid(cnt), block(64 * WR * WC);
-  if (a.n % 16 == 0)
-    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK>), grid, block, 0, st, a, c0);
-  else
-    hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, false, TRACK>), grid, block, 0, st, a, c0);
+  static_assert(CT == (MT <= 2 ? MT : 2) && WR == (MT <= 2 ? 4 : (MT <= 4 ? 2 : 1)),
+                "the host-side split count assumes this work split");
+  dim3 grid(cnt, a.splits), block(64 * WR * WC);
+  const bool exact = a.n % 16 == 0;
+  if (a.splits > 1) {
+    // long windows (>= 8 strips per row group, FP32, untracked): four strips
+    // per pass share each twiddle block of the uncached table
+    constexpr bool kRs = std::is_same<PR, PrecF32>::value && !TRACK;
+    if (kRs && exact && a.nb >= 8 * WR * a.splits)
+      hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK, true, kRs ? 4 : 1>), grid, block, 0, st, a, c0);
+    else if (exact)
+      hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK, true>), grid, block, 0, st, a, c0);
+    else
+      hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, false, TRACK, true>), grid, block, 0, st, a, c0);
+    hipLaunchKernelGGL(k_pie_project, dim3(cnt, 4), dim3(256), 0, st, a, c0);
+  } else {
+    if (exact)
+      hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK, false>), grid, block, 0, st, a, c0);
+    else
+      hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, false, TRACK, false>), grid, block, 0, st, a, c0);
+  }
 }
 
 template <class PR, int MT>
@@ -509,7 +579,16 @@ static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
     fwd_launch<PR, MT, true>(a, c0, cnt, st);
   else
     fwd_launch<PR, MT, false>(a, c0, cnt, st);
-  dim3 grid(cnt), block(64 * adj_waves(a.nb));
+  // column tiles of the adjoint over a second grid dimension when the chunk
+  // alone leaves compute units idle
+  const int nw = adj_waves(a.nb);
+  const int per = (a.nb + nw - 1) / nw;
+  int gy = 1;
+  if ((long)cnt * nw < 4L * a.num_cu) {
+    const long want = (4L * a.num_cu + (long)cnt * nw - 1) / ((long)cnt * nw);
+    gy = (int)(want < per ? want : per);
+  }
+  dim3 grid(cnt, gy), block(64 * nw);
   if (single)
     hipLaunchKernelGGL((k_pie_adjoint<PR, MT, true>), grid, block, 0, st, a, c0);
   else

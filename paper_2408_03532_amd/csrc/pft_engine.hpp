@@ -133,6 +133,102 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
   }
 }
 
+// Forward engine for long windows whose twiddle table does not stay in the
+// caches (n in the thousands): RS row strips per pass share every twiddle
+// block fetched, so the table streams NB / RS instead of NB times per wave.
+// The wave's strips are strip0, strip0 + sstep, ... taken RS at a time;
+// strips past NB in the last pass load rows of the pass's first strip and
+// their products are dropped.
+template <int MT, int CT, int RS, class Src, class Tab>
+__device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
+                                            f32x4 (&Yim)[MT][CT], int strip0, int sstep) {
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      Yre[a][b] = zero4();
+      Yim[a][b] = zero4();
+    }
+  for (int base = strip0; base < NB; base += sstep * RS) {
+    int rows[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int sr = base + r * sstep;
+      rows[r] = (sr < NB ? sr : base) * 16 + r16;
+    }
+    f32x4 Tre[RS][CT], Tim[RS][CT];
+#pragma unroll
+    for (int r = 0; r < RS; ++r)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        Tre[r][ct] = zero4();
+        Tim[r][ct] = zero4();
+      }
+    auto stage1 = [&](const c4(&a)[RS], const c4(&f)[CT]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+          const float ar = a[r].v[s].x, ai = a[r].v[s].y, nai = -ai;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            Tre[r][ct] = mfma4(ar, f[ct].v[s].x, Tre[r][ct]);
+            Tim[r][ct] = mfma4(ar, f[ct].v[s].y, Tim[r][ct]);
+          }
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            Tre[r][ct] = mfma4(nai, f[ct].v[s].y, Tre[r][ct]);
+            Tim[r][ct] = mfma4(ai, f[ct].v[s].x, Tim[r][ct]);
+          }
+        }
+    };
+    auto fetch = [&](int kb, c4(&a)[RS], c4(&f)[CT]) {
+#pragma unroll
+      for (int r = 0; r < RS; ++r) a[r] = src.load(rows[r], kb * 16 + 4 * g);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) f[ct] = FA.f32((size_t)(c2t0 + ct) * NB + kb, lane);
+    };
+    c4 a0[RS], a1[RS], f0[CT], f1[CT];
+    fetch(0, a0, f0);
+    int kb = 0;
+    for (; kb + 1 < NB; kb += 2) {
+      fetch(kb + 1, a1, f1);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a0, f0);
+      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a1, f1);
+    }
+    if (kb < NB) stage1(a0, f0);
+    // stage 2 per live strip: Y[c1 tile][own tiles] += F[c1 tile, strip] * T
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int sr = base + r * sstep;
+      if (sr >= NB) break;
+#pragma unroll
+      for (int c1t = 0; c1t < MT; ++c1t) {
+        const c4 fb = FA.f32((size_t)c1t * NB + sr, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float fr = fb.v[i].x, fi = fb.v[i].y, nfi = -fi;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            Yre[c1t][ct] = mfma4(fr, Tre[r][ct][i], Yre[c1t][ct]);
+            Yim[c1t][ct] = mfma4(fr, Tim[r][ct][i], Yim[c1t][ct]);
+          }
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            Yre[c1t][ct] = mfma4(nfi, Tim[r][ct][i], Yre[c1t][ct]);
+            Yim[c1t][ct] = mfma4(fi, Tre[r][ct][i], Yim[c1t][ct]);
+          }
+        }
+      }
+    }
+  }
+}
+
 // FP32 adjoint, stage 2 of column tile kt2 from the stage-1 accumulators S.
 template <int MT, int K1, class Sink, class Tab>
 __device__ __forceinline__ void adj_stage2_f32(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,

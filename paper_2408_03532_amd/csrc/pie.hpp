@@ -28,7 +28,8 @@ struct PieArgs {
   const void* ft;
   const float2* fft_tw;  // full-window fast transform twiddles (null: dense contraction)
   int prec;
-  float inv_n2;
+  int period;       // DFT length: n, or the masked field's size
+  float inv_n2;     // 1 / period^2 (inverse DFT of the band change)
   // parameters
   int norm, probe_step;
   float beta, gamma;
@@ -39,6 +40,9 @@ struct PieArgs {
   const float* amp; // [J][m][m]
   // workspace
   float2* R;        // [batch][m][m] residuals u' - u
+  float2* part;     // [batch][splits][m][m] partial spectra (row groups split over workgroups)
+  int splits;       // workgroups per position in the forward (1: whole window in one)
+  int num_cu;       // compute units of the device
   float2* dpsi;     // [batch][n][n] corrections (chunks of more than one position)
   double* phi_part; // [J][4]
   int32_t* rank;    // [J] place of each position in the sweep order
@@ -55,6 +59,27 @@ struct PieArgs {
 };
 
 constexpr int kStatBlocks = 512;
+
+// Forward work split of the dense sweep for MT = ceil(m/16) tiles per axis:
+// CT column tiles per wave, WC column groups, WR row groups per workgroup.
+inline int pie_ct(int mt) { return mt <= 2 ? mt : 2; }
+inline int pie_wc(int mt) { return (mt + pie_ct(mt) - 1) / pie_ct(mt); }
+inline int pie_wr_rt(int mt) { return mt <= 2 ? 4 : (mt <= 4 ? 2 : 1); }
+// Workgroups per position in the forward for chunks of `batch` positions:
+// few large windows split their row strips over more workgroups (partial
+// spectra summed by a projection kernel) until the chunk has about four
+// waves per compute unit, keeping at least one strip per row group, and
+// for long windows (nb >= 128) at least eight, so that passes of several
+// strips can share the twiddle blocks of the uncached table.
+inline int pie_row_splits(int nb, int mt, int batch, int num_cu) {
+  const long waves = (long)batch * pie_wc(mt) * pie_wr_rt(mt);
+  const long target = 4L * num_cu;
+  if (waves >= target) return 1;
+  long s = (target + waves - 1) / waves;
+  const long cap = nb >= 128 ? nb / (8 * pie_wr_rt(mt)) : nb / pie_wr_rt(mt);
+  if (s > cap) s = cap;
+  return s < 1 ? 1 : (int)s;
+}
 
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);

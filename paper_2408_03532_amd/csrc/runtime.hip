@@ -69,27 +69,37 @@ const char* pftpie_status_string(pftpie_status s) {
 const char* pftpie_last_error(void) { return g_last_error.c_str(); }
 
 pftpie_status pftpie_plan_create(int32_t n, int32_t m, pftpie_precision prec, pftpie_plan* out) {
-  return pftpie_plan_create_method(n, m, prec, PFTPIE_METHOD_AUTO, out);
+  return pftpie_plan_create_period(n, m, n, prec, PFTPIE_METHOD_AUTO, out);
 }
 
 pftpie_status pftpie_plan_create_method(int32_t n, int32_t m, pftpie_precision prec, pftpie_method method,
                                         pftpie_plan* out) {
+  return pftpie_plan_create_period(n, m, n, prec, method, out);
+}
+
+pftpie_status pftpie_plan_create_period(int32_t n, int32_t m, int32_t period, pftpie_precision prec,
+                                        pftpie_method method, pftpie_plan* out) {
   if (!out) return fail(PFTPIE_E_INVALID, "plan_create: out is NULL");
   *out = nullptr;
   if (method != PFTPIE_METHOD_AUTO && method != PFTPIE_METHOD_DENSE && method != PFTPIE_METHOD_FFT)
     return fail(PFTPIE_E_INVALID, "plan_create: unknown method");
-  if (n < 1 || n > kMaxN) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= n <= 4096");
+  if (n < 1 || n > kMaxN) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= n <= 8192");
   if (m < 1 || m > n) return fail(PFTPIE_E_INVALID, "plan_create: need 1 <= m <= n");
+  if (period < n || period > kMaxPeriod)
+    return fail(PFTPIE_E_INVALID, "plan_create: need n <= period <= 2^20");
   if (prec != PFTPIE_FP32 && prec != PFTPIE_SPLIT_BF16 && prec != PFTPIE_SPLIT_FP16)
     return fail(PFTPIE_E_INVALID, "plan_create: unknown precision");
   if (m > kMaxM) return fail(PFTPIE_E_UNSUPPORTED, "plan_create: m > 128 is not supported");
-  if (method == PFTPIE_METHOD_FFT && !fft_supported(n, m))
-    return fail(PFTPIE_E_UNSUPPORTED, "plan_create: the fast transform needs m = n in {16, 32, 64, 128}");
-  const bool use_fft = method == PFTPIE_METHOD_FFT || (method == PFTPIE_METHOD_AUTO && fft_supported(n, m));
+  const bool fft_ok = fft_supported(n, m) && period == n;
+  if (method == PFTPIE_METHOD_FFT && !fft_ok)
+    return fail(PFTPIE_E_UNSUPPORTED,
+                "plan_create: the fast transform needs m = n = period in {16, 32, 64, 128}");
+  const bool use_fft = method == PFTPIE_METHOD_FFT || (method == PFTPIE_METHOD_AUTO && fft_ok);
   pftpie_plan_s* p = new (std::nothrow) pftpie_plan_s();
   if (!p) return fail(PFTPIE_E_NOMEM, "plan_create: host allocation failed");
   p->n = n;
   p->m = m;
+  p->period = period;
   p->prec = prec;
   p->nb = ceil16(n);
   p->mt = ceil16(m);
@@ -122,13 +132,13 @@ pftpie_status pftpie_plan_create_method(int32_t n, int32_t m, pftpie_precision p
   const void* fa_src;
   const void* ft_src;
   if (prec == PFTPIE_FP32) {
-    build_twiddle_tables(n, m, p->fa_ctiles, fa, ft);
+    build_twiddle_tables(n, m, period, p->fa_ctiles, fa, ft);
     p->fa_bytes = fa.size() * sizeof(float);
     p->ft_bytes = ft.size() * sizeof(float);
     fa_src = fa.data();
     ft_src = ft.data();
   } else {
-    build_split_tables(n, m, p->fa_ctiles, prec == PFTPIE_SPLIT_BF16 ? 1 : 2, fa16, ft16);
+    build_split_tables(n, m, period, p->fa_ctiles, prec == PFTPIE_SPLIT_BF16 ? 1 : 2, fa16, ft16);
     p->fa_bytes = fa16.size() * sizeof(uint16_t);
     p->ft_bytes = ft16.size() * sizeof(uint16_t);
     fa_src = fa16.data();
@@ -172,6 +182,13 @@ pftpie_status pftpie_plan_destroy(pftpie_plan plan) {
   (void)hipFree(plan->ft);
   if (plan->fft_tw) (void)hipFree(plan->fft_tw);
   delete plan;
+  return PFTPIE_OK;
+}
+
+pftpie_status pftpie_plan_period(pftpie_plan plan, int32_t* period) {
+  if (pftpie_status s = check_plan(plan)) return s;
+  if (!period) return fail(PFTPIE_E_INVALID, "plan_period: period is NULL");
+  *period = plan->period;
   return PFTPIE_OK;
 }
 

@@ -16,7 +16,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace carve-up of one sweep; sizes in bytes, offsets 256-aligned.
 struct PieLayout {
-  size_t R, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxpart, maxes, red, stats, total;
+  size_t R, part, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxpart, maxes, red, stats, total;
+  int splits;
 };
 
 PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
@@ -31,6 +32,8 @@ PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
     return o;
   };
   L.R = take((size_t)batch * p->m * p->m * 8);
+  L.splits = p->method == PFTPIE_METHOD_FFT ? 1 : pie_row_splits(p->nb, p->mt, batch, p->num_cu);
+  L.part = L.splits > 1 ? take((size_t)batch * L.splits * p->m * p->m * 8) : SIZE_MAX;
   L.dpsi = multi ? take((size_t)batch * nn * 8) : SIZE_MAX;
   L.phi = take((size_t)s->J * 4 * 8);
   L.rank = take((size_t)s->J * 4);
@@ -222,7 +225,8 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.ft = pl->ft;
   a.fft_tw = pl->method == PFTPIE_METHOD_FFT ? static_cast<const float2*>(pl->fft_tw) : nullptr;
   a.prec = pl->prec;
-  a.inv_n2 = (float)(1.0 / ((double)pl->n * pl->n));
+  a.period = pl->period;
+  a.inv_n2 = (float)(1.0 / ((double)pl->period * pl->period));
   a.norm = p->norm;
   a.probe_step = probe_step;
   a.beta = p->beta;
@@ -232,6 +236,9 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.P = static_cast<float2*>(probe);
   a.amp = amp;
   a.R = static_cast<float2*>(at(L.R));
+  a.part = static_cast<float2*>(at(L.part));
+  a.splits = L.splits;
+  a.num_cu = pl->num_cu;
   a.dpsi = static_cast<float2*>(at(L.dpsi));
   a.phi_part = static_cast<double*>(at(L.phi));
   a.rank = static_cast<int32_t*>(at(L.rank));

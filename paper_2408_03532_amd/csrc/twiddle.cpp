@@ -1,8 +1,9 @@
-// Partial DFT matrix F_m[c][k] = exp(-2 pi i t_c k / n), t_c = c - floor(m/2)
-// (the DFT kernel of Sec. 3.1.1 restricted to the kept window), built in
-// double and laid out in the kernels' tile order.  The phase t_c * k is
-// reduced modulo n in 64-bit integers before the trigonometric call so the
-// angle stays in [0, 2 pi) whatever the sizes.
+// Partial DFT matrix F_m[c][k] = exp(-2 pi i t_c k / N), t_c = c - floor(m/2),
+// k < n (the DFT kernel of Sec. 3.1.1 restricted to the kept window; N = n,
+// or the DFT length of a masked larger field, Sec. 4.2), built in double and
+// laid out in the kernels' tile order.  The phase t_c * k is reduced modulo
+// N in 64-bit integers before the trigonometric call so the angle stays in
+// [0, 2 pi) whatever the sizes.
 #include <cmath>
 #include <cstring>
 #include <cstdint>
@@ -18,12 +19,14 @@ struct cd {
   double re, im;
 };
 
-cd twiddle(int n, int m, int c, int k) {
+// Entry (c, k) of the n-column partial DFT matrix of DFT length `period`
+// (period > n: the window of a masked larger field).
+cd twiddle(int n, int m, int period, int c, int k) {
   if (c >= m || k >= n) return {0.0, 0.0};
   const int64_t t = (int64_t)c - (int64_t)(m / 2);
-  int64_t p = (t * (int64_t)k) % n;
-  if (p < 0) p += n;
-  const double ang = 2.0 * M_PI * (double)p / (double)n;
+  int64_t p = (t * (int64_t)k) % period;
+  if (p < 0) p += period;
+  const double ang = 2.0 * M_PI * (double)p / (double)period;
   return {std::cos(ang), -std::sin(ang)};
 }
 
@@ -43,19 +46,20 @@ void put_block(float* blk, F entry) {
 
 }  // namespace
 
-void build_twiddle_tables(int n, int m, int fa_ctiles, std::vector<float>& fa, std::vector<float>& ft) {
+void build_twiddle_tables(int n, int m, int period, int fa_ctiles, std::vector<float>& fa,
+                          std::vector<float>& ft) {
   const int nb = ceil16(n), mt = ceil16(m);
   fa.assign((size_t)fa_ctiles * nb * 128 * 4, 0.f);
   ft.assign((size_t)nb * mt * 128 * 4, 0.f);
   for (int ct = 0; ct < fa_ctiles; ++ct)
     for (int kb = 0; kb < nb; ++kb)
       put_block(&fa[((size_t)ct * nb + kb) * 512], [&](int r16, int g, int s) {
-        return twiddle(n, m, ct * 16 + r16, kb * 16 + 4 * g + s);
+        return twiddle(n, m, period, ct * 16 + r16, kb * 16 + 4 * g + s);
       });
   for (int kt = 0; kt < nb; ++kt)
     for (int cb = 0; cb < mt; ++cb)
       put_block(&ft[((size_t)kt * mt + cb) * 512], [&](int r16, int g, int s) {
-        return twiddle(n, m, cb * 16 + 4 * g + s, kt * 16 + r16);
+        return twiddle(n, m, period, cb * 16 + 4 * g + s, kt * 16 + r16);
       });
 }
 
@@ -155,7 +159,7 @@ void put_split_block(uint16_t* blk, int kind, F entry) {
 
 }  // namespace
 
-void build_split_tables(int n, int m, int fa_ctiles, int kind, std::vector<uint16_t>& fa,
+void build_split_tables(int n, int m, int period, int fa_ctiles, int kind, std::vector<uint16_t>& fa,
                         std::vector<uint16_t>& ft) {
   const int nb = ceil16(n), mt = ceil16(m);
   fa.assign((size_t)fa_ctiles * nb * 1024, 0);
@@ -163,12 +167,12 @@ void build_split_tables(int n, int m, int fa_ctiles, int kind, std::vector<uint1
   for (int ct = 0; ct < fa_ctiles; ++ct)
     for (int kb = 0; kb < nb; ++kb)
       put_split_block(&fa[((size_t)ct * nb + kb) * 1024], kind, [&](int r16, int g, int s) {
-        return twiddle(n, m, ct * 16 + r16, kb * 16 + 4 * g + s);
+        return twiddle(n, m, period, ct * 16 + r16, kb * 16 + 4 * g + s);
       });
   for (int kt = 0; kt < nb; ++kt)
     for (int cb = 0; cb < mt; ++cb)
       put_split_block(&ft[((size_t)kt * mt + cb) * 1024], kind, [&](int r16, int g, int s) {
-        return twiddle(n, m, cb * 16 + 4 * g + s, kt * 16 + r16);
+        return twiddle(n, m, period, cb * 16 + 4 * g + s, kt * 16 + r16);
       });
 }
 

@@ -38,9 +38,10 @@ class Plan:
 
     method: "auto" (the fast full-window transform when m = n in
     {16, 32, 64, 128}, else the dense contraction), "dense" or "fft"; the
-    resolved choice is in ``self.method``."""
+    resolved choice is in ``self.method``.  period: DFT length of a masked
+    larger field (default n; see pftpie_plan_create_period)."""
 
-    def __init__(self, n, m, precision="fp32", device=None, method="auto"):
+    def __init__(self, n, m, precision="fp32", device=None, method="auto", period=None):
         if precision not in _lib.PRECISION:
             raise ValueError(f"precision must be one of {sorted(_lib.PRECISION)}")
         if method not in _lib.METHOD:
@@ -48,10 +49,11 @@ class Plan:
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else
                            torch.device(device).index or 0)
         self.n, self.m, self.precision, self.device = int(n), int(m), precision, dev
+        self.period = int(n) if period is None else int(period)
         h = _lib.c_plan()
         with torch.cuda.device(dev):
-            _lib.call("pftpie_plan_create_method", n, m, _lib.PRECISION[precision], _lib.METHOD[method],
-                      ctypes.byref(h))
+            _lib.call("pftpie_plan_create_period", n, m, self.period, _lib.PRECISION[precision],
+                      _lib.METHOD[method], ctypes.byref(h))
         self.handle = h
         resolved = ctypes.c_int32()
         _lib.call("pftpie_plan_method", self.handle, ctypes.byref(resolved))
@@ -101,14 +103,15 @@ class Plan:
         return out
 
 
-def get_plan(n, m, precision="fp32", device=None, method="auto"):
-    """Cached plan for (device, n, m, precision, method)."""
+def get_plan(n, m, precision="fp32", device=None, method="auto", period=None):
+    """Cached plan for (device, n, m, precision, method, period)."""
     dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
-    key = (dev, int(n), int(m), precision, method)
+    period = int(n) if period is None else int(period)
+    key = (dev, int(n), int(m), precision, method, period)
     with _plans_lock:
         p = _plans.get(key)
         if p is None:
-            p = Plan(n, m, precision, device=torch.device("cuda", dev), method=method)
+            p = Plan(n, m, precision, device=torch.device("cuda", dev), method=method, period=period)
             _plans[key] = p
         return p
 

@@ -34,17 +34,17 @@ class PieParams:
 
 class Scan:
     """Scan positions (top-left (row, col) of each n x n window) inside an
-    H x W object, bound to the plan of (n, m, precision, method); see
-    ``pft.Plan`` for the method."""
+    H x W object, bound to the plan of (n, m, precision, method, period); see
+    ``pft.Plan`` for the method and the masked-field period."""
 
-    def __init__(self, pos, obj_shape, n, m, precision="fp32", device=None, method="auto"):
+    def __init__(self, pos, obj_shape, n, m, precision="fp32", device=None, method="auto", period=None):
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
         if pos.ndim != 2 or pos.shape[1] != 2:
             raise ValueError("pos must be [J][2]")
         self.pos = pos
         self.J = pos.shape[0]
         self.H, self.W = (int(v) for v in obj_shape)
-        self.plan = get_plan(n, m, precision, device, method)
+        self.plan = get_plan(n, m, precision, device, method, period)
         self.n, self.m, self.precision = self.plan.n, self.plan.m, precision
         h = _lib.c_scan()
         with torch.cuda.device(self.plan.device):

@@ -36,8 +36,8 @@ def test_status_strings():
     assert L.pftpie_status_string(99) == b"unknown status"
 
 
-@pytest.mark.parametrize("n,m,prec,msg", [(0, 1, 0, b"n <= 4096"), (8, 9, 0, b"m <= n"), (8, 0, 0, b"m <= n"),
-                                          (5000, 4, 0, b"n <= 4096"), (8, 4, 7, b"unknown precision")])
+@pytest.mark.parametrize("n,m,prec,msg", [(0, 1, 0, b"n <= 8192"), (8, 9, 0, b"m <= n"), (8, 0, 0, b"m <= n"),
+                                          (9000, 4, 0, b"n <= 8192"), (8, 4, 7, b"unknown precision")])
 def test_plan_create_rejects_bad_sizes_before_the_device(n, m, prec, msg):
     L = pk.lib()
     h = ctypes.c_void_p(123)
@@ -54,14 +54,27 @@ def test_plan_create_large_window_is_unsupported():
 
 @pytest.mark.parametrize("n,m,method,status,msg", [
     (32, 32, 7, 1, b"unknown method"),
-    (64, 32, 2, 2, b"m = n in {16, 32, 64, 128}"),   # the fast transform needs the full window
+    (64, 32, 2, 2, b"in {16, 32, 64, 128}"),   # the fast transform needs the full window
     (256, 256, 2, 2, b"m > 128"),                    # windows above 128 are not built
-    (48, 48, 2, 2, b"m = n in {16, 32, 64, 128}"),   # not a supported length
+    (48, 48, 2, 2, b"in {16, 32, 64, 128}"),   # not a supported length
 ])
 def test_plan_method_rejected_on_the_host(n, m, method, status, msg):
     L = pk.lib()
     h = ctypes.c_void_p(123)
     assert L.pftpie_plan_create_method(n, m, 0, method, ctypes.byref(h)) == status
+    assert h.value is None
+    assert msg in L.pftpie_last_error()
+
+
+@pytest.mark.parametrize("n,m,period,method,status,msg", [
+    (32, 16, 31, 0, 1, b"n <= period"),          # the field cannot be smaller than the window
+    (32, 16, (1 << 20) + 1, 0, 1, b"period <= 2^20"),
+    (32, 32, 64, 2, 2, b"m = n = period"),       # the fast transform is for the window's own period
+])
+def test_plan_period_rejected_on_the_host(n, m, period, method, status, msg):
+    L = pk.lib()
+    h = ctypes.c_void_p(123)
+    assert L.pftpie_plan_create_period(n, m, period, 0, method, ctypes.byref(h)) == status
     assert h.value is None
     assert msg in L.pftpie_last_error()
 

@@ -57,3 +57,22 @@ def test_poisson_scaling_hits_the_photon_budget():
     counts = noisy.astype(np.float64) * s
     assert np.allclose(counts, np.round(counts), atol=1e-2)
     assert abs(counts.sum(axis=(1, 2)).mean() / 1e4 - 1) < 0.01
+
+
+def test_masked_field_recipe_small():
+    from oracle import pft
+    c = workloads.masked_field(field=256, m=32, coarse=32, sigma_f=4.0)
+    n = 128
+    assert c["obj"].shape == (256, 256) and c["probe"].shape == (n, n) and c["amp"].shape == (9, 32, 32)
+    assert np.allclose(np.abs(c["obj"]), 1.0, atol=1e-6)
+    # serpentine scan: down the first column, up the second, down the third
+    assert c["pos"].tolist() == [[0, 0], [64, 0], [128, 0], [128, 64], [64, 64], [0, 64],
+                                 [0, 128], [64, 128], [128, 128]]
+    # amplitudes: magnitudes of the kept coefficients of the masked field's
+    # 256-point DFT (the oracle's transform with period and window shift)
+    for j in (0, 4, 8):
+        r, col = c["pos"][j]
+        u = pft.forward(c["probe"] * c["obj"][r:r + n, col:col + n], 32, period=256, shift=(r, col))
+        assert np.max(np.abs(np.abs(u) - c["amp"][j])) <= 1e-6 * np.max(np.abs(u))
+    sub = workloads.masked_field(field=256, m=32, coarse=32, sigma_f=4.0, amp_positions=[4], with_init=False)
+    assert sub["init"] is None and np.array_equal(sub["amp"][0], c["amp"][4])

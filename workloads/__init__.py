@@ -262,3 +262,59 @@ def adjoint_descs(desc):
     m x m coefficient blocks, outputs the n x n patches."""
     d = np.asarray(desc, dtype=np.int64)
     return np.stack([d[:, 0], d[:, 1], d[:, 3], d[:, 2]], axis=1)
+
+
+def serpentine(k, step):
+    """k x k window corners, column by column: down the first column, up the
+    second, down the third, ... (the scan of the non-blind experiments,
+    Sec. 4.2), as (row, col) offsets [k*k][2]."""
+    pos = []
+    for ix in range(k):
+        rows = range(k) if ix % 2 == 0 else range(k - 1, -1, -1)
+        pos += [(step * iy, step * ix) for iy in rows]
+    return np.asarray(pos, dtype=np.int32)
+
+
+def masked_field_amplitudes(field_img, probe, pos, m, period, workers=-1):
+    """|kept m x m coefficients| of the period-point 2-D DFT of each masked
+    field (probe on the window at pos[j], zero elsewhere), float32 [J][m][m].
+    The window's position only multiplies the coefficients by a phase, so
+    each window is transformed at the origin: zero-padded row transforms of
+    length `period` keep the m centred columns, then zero-padded column
+    transforms keep the m centred rows (library FFT, complex64)."""
+    import scipy.fft as sfft
+    n = probe.shape[0]
+    keep = (np.arange(m) - m // 2) % period
+    out = np.empty((len(pos), m, m), dtype=np.float32)
+    for j, (r, c) in enumerate(pos):
+        rows = np.empty((n, m), dtype=np.complex64)
+        for r0 in range(0, n, 512):
+            blk = probe[r0:r0 + 512] * field_img[r + r0:r + r0 + min(512, n - r0), c:c + n]
+            rows[r0:r0 + 512] = sfft.fft(blk, n=period, axis=1, workers=workers)[:, keep]
+        out[j] = np.abs(sfft.fft(rows, n=period, axis=0, workers=workers)[keep, :])
+    return out
+
+
+def masked_field(seed=6, field=16384, m=128, coarse=1024, sigma_f=24.0, amp_positions=None, with_init=True):
+    """Non-blind masked-field workload (the large experiment of Sec. 4.2):
+    a field x field pure-phase object (smooth random phase made on a
+    coarse x coarse grid with sigma_f px and interpolated bilinearly),
+    identity probe on field/2 x field/2 windows, 3 x 3 serpentine scan with
+    shift field/4 (9 positions, 50 % overlap), noise-free amplitudes of the
+    centred m x m coefficients of each masked field's field-point DFT, and a
+    random initial object.  amp_positions (indices into pos) limits the
+    amplitudes to those windows; with_init=False skips the initial object."""
+    from scipy.ndimage import zoom
+    rs = streams(seed)
+    n = field // 2
+    ph = np.angle(smooth_phase_object(rs[0], coarse, coarse, sigma_f)).astype(np.float32)
+    ph = zoom(ph, field / coarse, order=1, mode="grid-wrap", grid_mode=True)
+    obj = np.exp(1j * ph).astype(np.complex64)
+    del ph
+    probe = np.ones((n, n), dtype=np.complex64)
+    pos = serpentine(3, field // 4)
+    sel = pos if amp_positions is None else pos[np.asarray(amp_positions)]
+    amp = masked_field_amplitudes(obj, probe, sel, m, field)
+    init = random_init(rs[4], field, field) if with_init else None
+    return dict(obj=obj, probe=probe, pos=pos, amp=amp, m=m, period=field, init=init)
+
