@@ -62,7 +62,7 @@ def amplitudes(intensity, m):
 
 
 def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
-              beta=1.0, gamma=0.0, alpha=1e-3, period=None):
+              beta=1.0, gamma=0.0, alpha=1e-3, period=None, probe_update="simultaneous"):
     """One PIE / ePIE iteration (Sec. 2.1, eqs. (5)-(6)) over all positions.
 
     obj   [H][W] complex, probe [n][n] complex, pos [J][2] integer top-left
@@ -85,7 +85,20 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
     F_m^H (...) conj(F_m) / N^2 with the conjugate ramp; phi is normalised
     by J N^2.  The ramp is applied literally here even though it cancels
     (the projection keeps it, the adjoint removes it).
+
+    probe_update: "simultaneous" (default) evaluates the probe step of
+    eq. (6) with the object and residual of the object step; "literal"
+    takes eq. (6) as printed: after the object step of position j, the exit
+    wave is formed again from the updated object, projected again, and the
+    probe moves along conj(z_j^{k+1}) times that new residual.  The literal
+    form is defined for single-position chunks without normalisation
+    (batch = 1, norm = 0), which is what eqs. (5)-(6) describe.
     """
+    if probe_update not in ("simultaneous", "literal"):
+        raise ValueError("probe_update must be 'simultaneous' or 'literal'")
+    literal = probe_update == "literal" and gamma > 0.0
+    if literal and (batch != 1 or norm != 0):
+        raise ValueError("the literal probe update is defined for batch = 1, norm = 0")
     O = np.asarray(obj).astype(np.complex128).copy()
     P = np.asarray(probe).astype(np.complex128).copy()
     pos = np.asarray(pos, dtype=np.int64)
@@ -113,12 +126,21 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
             delta = pft.adjoint(up - u, n, N, shift) / float(N * N)  # P_M(psi) - psi
             numO[r:r + n, c:c + n] += np.conj(P) * delta
             D[r:r + n, c:c + n] += np.abs(P) ** 2
-            if gamma > 0.0:
+            if gamma > 0.0 and not literal:
                 numP += np.conj(Oj) * delta
                 E += np.abs(Oj) ** 2
         if norm == 0:
             O = O + beta * numO
-            if gamma > 0.0:
+            if literal:
+                # eq. (6) at the updated object: new exit wave, new projection
+                (j,) = chunk
+                r, c = pos[j]
+                Oj = O[r:r + n, c:c + n]
+                shift = None if period is None else (r, c)
+                u = pft.forward(P * Oj, m, N, shift)
+                delta = pft.adjoint(project(u, amp[j]) - u, n, N, shift) / float(N * N)
+                P = P + gamma * np.conj(Oj) * delta
+            elif gamma > 0.0:
                 P = P + gamma * numP
         else:
             O = O + beta * numO / (D + alpha * D.max())

@@ -110,6 +110,46 @@ def test_sequential_full_window_probe_step_equals_paper_simultaneous_form():
     assert np.linalg.norm(gw - w) / np.linalg.norm(w) < 1e-13
 
 
+def test_sequential_full_window_probe_step_equals_paper_literal_form():
+    """eq. (6) as printed: the probe step at the updated object z_j^{k+1}
+    with a recomputed projection (library FFT on the full window)."""
+    obj, probe, pos, inten = small_case(2, grid=2)
+    d = np.sqrt(inten)
+    z0 = obj * 0.8
+    w0 = probe * (1 + 0.1 * rnd(probe.shape, 4))
+    n = probe.shape[0]
+    beta, gamma = 0.7, 0.3
+    order = np.array([3, 0, 2, 1])
+    gz, gw, _ = pie.pie_sweep(z0, w0, pos, d, n, order=order, batch=1, norm=0, beta=beta, gamma=gamma,
+                              probe_update="literal")
+
+    def residual(ex, dj):
+        spec = np.fft.fftshift(np.fft.fft2(ex))
+        return ex - np.fft.ifft2(np.fft.ifftshift(dj * np.exp(1j * np.angle(spec))))
+
+    z, w = z0.copy(), w0.copy()
+    for j in order:
+        r, c = pos[j]
+        zj = z[r:r + n, c:c + n]
+        z[r:r + n, c:c + n] = zj - beta * np.conj(w) * residual(w * zj, d[j])      # eq. (5)
+        zj1 = z[r:r + n, c:c + n]
+        w = w - gamma * np.conj(zj1) * residual(w * zj1, d[j])                     # eq. (6)
+    assert np.linalg.norm(gz - z) / np.linalg.norm(z) < 1e-13
+    assert np.linalg.norm(gw - w) / np.linalg.norm(w) < 1e-13
+    # and it differs from the simultaneous reading
+    _, gs, _ = pie.pie_sweep(z0, w0, pos, d, n, order=order, batch=1, norm=0, beta=beta, gamma=gamma)
+    assert np.linalg.norm(gs - w) / np.linalg.norm(w) > 1e-6
+
+
+def test_literal_probe_update_only_for_sequential_plain_steps():
+    obj, probe, pos, inten = small_case(1)
+    d = np.sqrt(inten)
+    with pytest.raises(ValueError):
+        pie.pie_sweep(obj, probe, pos, d, 8, batch=2, gamma=0.5, probe_update="literal")
+    with pytest.raises(ValueError):
+        pie.pie_sweep(obj, probe, pos, d, 8, norm=1, gamma=0.5, probe_update="literal")
+
+
 @pytest.mark.parametrize("m,batch,norm,gamma", [(16, 1, 0, 0.0), (8, 9, 1, 0.0), (6, 4, 1, 0.5),
                                                 (5, 1, 0, 1.0), (16, 9, 0, 0.2)])
 def test_fixed_point_of_noise_free_data(m, batch, norm, gamma):
