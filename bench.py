@@ -186,6 +186,25 @@ def masked_field_rate(torch, pk, precision="fp32", sweeps=5, warmup=1):
             "phi_last": float(stats[0].item())}
 
 
+def epie_blind_rate(torch, pk, m, sweeps=10, warmup=2):
+    """Blind ePIE sweeps on the circular-window geometry (16 windows of
+    128^2, 278^2 object), probe step of eq. (6) at the updated object (two
+    transform pairs per position), one random order."""
+    import numpy as np
+    import workloads
+    case = workloads.blind_circular()
+    scan = pk.Scan(case["pos"], case["init"].shape, 128, m)
+    amp = pk.crop_amplitudes(torch.from_numpy(case["intensity"]).cuda(), m)
+    O = torch.from_numpy(case["init"]).cuda()
+    P = torch.from_numpy(case["probe_init"]).cuda()
+    order = torch.from_numpy(np.random.default_rng(3).permutation(16).astype(np.int32)).cuda()
+    prm = pk.PieParams(batch=1, norm=0, beta=0.5, gamma=0.1, probe_update="literal")
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ms = time_calls(torch, lambda: pk.pie_sweep(O, P, scan, amp, prm, order=order, stats=stats), sweeps, warmup)
+    return {"iters_per_s": 1e3 / ms, "ms_per_sweep": ms, "positions": 16, "n": 128, "m": m,
+            "method": scan.plan.method}
+
+
 def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
     import workloads
     case = workloads.tiny_pie()
@@ -328,6 +347,8 @@ def main():
         extra["pie_at_scale_phase2_fft"] = pie_at_scale_rate(torch, pk, "fp32", m=128)
         extra["pie_at_scale_phase2_dense"] = pie_at_scale_rate(torch, pk, "fp32", m=128, method="dense")
         extra["pie_masked_field_16384"] = masked_field_rate(torch, pk)
+        extra["epie_blind_circular_m32"] = epie_blind_rate(torch, pk, 32)
+        extra["epie_blind_circular_m128"] = epie_blind_rate(torch, pk, 128)
         extra["pie_tiny_sequential"] = pie_tiny_rate(torch, pk, 1, 0)
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])

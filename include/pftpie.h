@@ -192,6 +192,11 @@ typedef struct {
   float beta;     /* object step */
   float gamma;    /* probe step; 0 = probe fixed (non-blind PIE) */
   float alpha;    /* denominator regulariser relative to the max (norm == 1) */
+  int32_t probe_update; /* probe step of eq. (6), gamma > 0: 0 = evaluated with
+                     the object and residual of the object step; 1 = as
+                     printed, at the updated object with the exit wave and
+                     projection formed again (a second transform pair per
+                     position; needs batch == 1 and norm == 0) */
 } pie_params;
 
 /* Bytes of device workspace pie_sweep needs for these parameters. */

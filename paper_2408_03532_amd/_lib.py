@@ -27,7 +27,8 @@ METHOD = {"auto": 0, "dense": 1, "fft": 2}
 
 
 class PieParams(ctypes.Structure):
-    _fields_ = [("batch", i32), ("norm", i32), ("beta", f32), ("gamma", f32), ("alpha", f32)]
+    _fields_ = [("batch", i32), ("norm", i32), ("beta", f32), ("gamma", f32), ("alpha", f32),
+                ("probe_update", i32)]
 
 
 class Desc(ctypes.Structure):

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(fft_threads<G>()) void k_pie_fft(PieArgs a, int c0)
     red_max[1][w] = mo;
   }
   fft2_inverse_head<G>(buf, tw);  // starts with a barrier: the partials are visible
-  if (threadIdx.x == 0 && valid) {
+  if (threadIdx.x == 0 && valid && !a.probe_pass) {
     double s = 0.0;
     for (int k = 0; k < nw; ++k) s += red_phi[k];
     a.phi_part[(size_t)j * 4] = s;
@@ -213,6 +213,11 @@ __global__ __launch_bounds__(fft_threads<G>()) void k_pie_fft(PieArgs a, int c0)
         const size_t oi = (size_t)(ps.x + row) * a.W + ps.y + col;
         const float2 p = a.P[pi];
         const float2 ov = a.O[oi];
+        if (a.probe_pass) {  // probe step at the updated object, O unchanged
+          const float2 vp = cmulc(ov, d);
+          a.P[pi] = make_float2(p.x + a.gamma * vp.x, p.y + a.gamma * vp.y);
+          continue;
+        }
         float so = a.beta;
         if (a.norm) {
           const double p2 = (double)p.x * p.x + (double)p.y * p.y;

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
       }
     }
   phi = wave_sum(phi);
-  if (lane == 0 && valid) a.phi_part[(size_t)j * 4 + wc] = phi;
+  if (lane == 0 && valid && !a.probe_pass) a.phi_part[(size_t)j * 4 + wc] = phi;
 }
 
 // Sum of the partial spectra of chunk entry q (fixed order over the splits)
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_pie_project(PieArgs a, int c0) {
   phi = wave_sum(phi);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = phi;
   __syncthreads();
-  if (threadIdx.x == 0 && valid) a.phi_part[(size_t)j * 4 + blockIdx.y] = sh[0] + sh[1] + sh[2] + sh[3];
+  if (threadIdx.x == 0 && valid && !a.probe_pass) a.phi_part[(size_t)j * 4 + blockIdx.y] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Residual source of the adjoint (m x m, masked).
@@ -225,11 +225,13 @@ struct ResSrc {
 // Single-position chunk: O[window] += beta conj(P) dpsi / (|P|^2 + alpha max |P|^2)
 // (denominator only with norm), and with a probe step
 // P += gamma conj(O_j) dpsi / (|O_j|^2 + alpha max |O_j|^2), both from the
-// values before this position's update.  Each pixel belongs to one lane.
+// values before this position's update.  probe_pass: the second pass of the
+// probe step at the updated object (eq. (6) as printed): P += gamma conj(O_j)
+// dpsi only, O unchanged.  Each pixel belongs to one lane.
 struct UpdateSink {
   float2* __restrict__ O;
   float2* __restrict__ P;
-  int n, W, r, c, norm, probe_step, valid;
+  int n, W, r, c, norm, probe_step, valid, probe_pass;
   float inv, beta, gamma;
   double regP, regO;  // alpha * max |P|^2, alpha * max |O_j|^2
   template <bool TR>
@@ -246,6 +248,11 @@ struct UpdateSink {
         const size_t o = (size_t)(r + k1) * W + (c + k2);
         const float2 p = P[pi];
         const float2 ov = O[o];
+        if (probe_pass) {
+          const float2 vp = cmulc(ov, d);
+          P[pi] = make_float2(p.x + gamma * vp.x, p.y + gamma * vp.y);
+          continue;
+        }
         float so = beta;
         if (norm) {
           const double p2 = (double)p.x * p.x + (double)p.y * p.y;
@@ -298,7 +305,7 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
       regP = a.alpha * (double)__uint_as_float(a.winmax[2 * j]);
       regO = a.alpha * (double)__uint_as_float(a.winmax[2 * j + 1]);
     }
-    UpdateSink sink{a.O, a.P, a.n, a.W, ps.x, ps.y, a.norm, a.probe_step, (int)valid,
+    UpdateSink sink{a.O, a.P, a.n, a.W, ps.x, ps.y, a.norm, a.probe_step, (int)valid, a.probe_pass,
                     a.inv_n2, a.beta, a.gamma, regP, regO};
     for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
   } else {
@@ -617,23 +624,34 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   hipLaunchKernelGGL(k_pie_begin, dim3(ew_blocks(obj)), dim3(256), 0, st, a);
   const int ntiles = a.tiles_x * a.tiles_y;
   const int pblocks = pie_probe_blocks(a.n);
+  auto run_chunk = [&](const PieArgs& ca, int c0, int cnt) -> hipError_t {
+    if (ca.fft_tw) return launch_pie_fft_chunk(ca, c0, cnt, st);
+    switch (ca.mt) {
+      case 1: chunk_mt<1>(ca, c0, cnt, st); break;
+      case 2: chunk_mt<2>(ca, c0, cnt, st); break;
+      case 3: chunk_mt<3>(ca, c0, cnt, st); break;
+      case 4: chunk_mt<4>(ca, c0, cnt, st); break;
+      case 5: chunk_mt<5>(ca, c0, cnt, st); break;
+      case 6: chunk_mt<6>(ca, c0, cnt, st); break;
+      case 7: chunk_mt<7>(ca, c0, cnt, st); break;
+      case 8: chunk_mt<8>(ca, c0, cnt, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+  };
+  // eq. (6) as printed (single positions): the object step, then a second
+  // transform pair at the updated object for the probe step
+  PieArgs obj_pass = a, probe_pass = a;
+  obj_pass.probe_step = 0;
+  probe_pass.probe_pass = 1;
   for (int c0 = 0; c0 < a.J; c0 += batch) {
     const int cnt = (a.J - c0 < batch) ? a.J - c0 : batch;
-    if (a.fft_tw) {
-      const hipError_t e = launch_pie_fft_chunk(a, c0, cnt, st);
-      if (e != hipSuccess) return e;
-    } else {
-      switch (a.mt) {
-        case 1: chunk_mt<1>(a, c0, cnt, st); break;
-        case 2: chunk_mt<2>(a, c0, cnt, st); break;
-        case 3: chunk_mt<3>(a, c0, cnt, st); break;
-        case 4: chunk_mt<4>(a, c0, cnt, st); break;
-        case 5: chunk_mt<5>(a, c0, cnt, st); break;
-        case 6: chunk_mt<6>(a, c0, cnt, st); break;
-        case 7: chunk_mt<7>(a, c0, cnt, st); break;
-        case 8: chunk_mt<8>(a, c0, cnt, st); break;
-        default: return hipErrorInvalidValue;
-      }
+    hipError_t e;
+    if (a.probe_literal) {
+      if ((e = run_chunk(obj_pass, c0, cnt)) != hipSuccess) return e;
+      if ((e = run_chunk(probe_pass, c0, cnt)) != hipSuccess) return e;
+    } else if ((e = run_chunk(a, c0, cnt)) != hipSuccess) {
+      return e;
     }
     if (cnt == 1) continue;  // updated in place
     if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt);

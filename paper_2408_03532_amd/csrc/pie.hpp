@@ -32,6 +32,8 @@ struct PieArgs {
   float inv_n2;     // 1 / period^2 (inverse DFT of the band change)
   // parameters
   int norm, probe_step;
+  int probe_literal;  // probe step of eq. (6) at the updated object (second pass)
+  int probe_pass;     // 1: this launch is that second pass (probe only, no objective)
   float beta, gamma;
   double alpha;
   // data

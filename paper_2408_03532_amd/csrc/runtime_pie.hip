@@ -59,6 +59,9 @@ pftpie_status check_params(const pie_scan_s* s, const pie_params* p) {
   if (!std::isfinite(p->beta) || !std::isfinite(p->gamma) || !std::isfinite(p->alpha))
     return fail(PFTPIE_E_INVALID, "pie: non-finite step or regulariser");
   if (p->gamma < 0.f || p->alpha < 0.f) return fail(PFTPIE_E_INVALID, "pie: gamma and alpha must be >= 0");
+  if (p->probe_update != 0 && p->probe_update != 1) return fail(PFTPIE_E_INVALID, "pie: probe_update must be 0 or 1");
+  if (p->probe_update == 1 && p->gamma > 0.f && (p->batch != 1 || p->norm != 0))
+    return fail(PFTPIE_E_INVALID, "pie: the probe update at the updated object needs batch == 1 and norm == 0");
   return PFTPIE_OK;
 }
 
@@ -229,6 +232,8 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
   a.inv_n2 = (float)(1.0 / ((double)pl->period * pl->period));
   a.norm = p->norm;
   a.probe_step = probe_step;
+  a.probe_literal = probe_step && p->probe_update == 1;
+  a.probe_pass = 0;
   a.beta = p->beta;
   a.gamma = p->gamma;
   a.alpha = p->alpha;

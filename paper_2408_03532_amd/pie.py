@@ -20,16 +20,23 @@ from .pft import _require, _stream_ptr, get_plan
 class PieParams:
     """batch: positions per chunk (1 = sequential eq. (5), J = fully batched);
     norm: 0 plain step, 1 overlap-normalised; beta / gamma: object / probe
-    steps (gamma = 0: probe fixed); alpha: denominator regulariser."""
+    steps (gamma = 0: probe fixed); alpha: denominator regulariser;
+    probe_update: "simultaneous" (eq. (6) with the object and residual of
+    the object step) or "literal" (eq. (6) as printed, at the updated object;
+    batch 1, norm 0)."""
     batch: int = 1
     norm: int = 0
     beta: float = 1.0
     gamma: float = 0.0
     alpha: float = 1e-3
+    probe_update: str = "simultaneous"
 
     def c(self):
+        modes = {"simultaneous": 0, "literal": 1}
+        if self.probe_update not in modes:
+            raise ValueError("probe_update must be 'simultaneous' or 'literal'")
         return _lib.PieParams(int(self.batch), int(self.norm), float(self.beta), float(self.gamma),
-                              float(self.alpha))
+                              float(self.alpha), modes[self.probe_update])
 
 
 class Scan:
@@ -129,7 +136,7 @@ def rel_change(stats_host):
 
 def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_full=100,
                tol_full=5e-4, params=None, full_params=None, order=None, callback=None,
-               precision="fp32", full_method="auto"):
+               precision="fp32", full_method="auto", order_seed=0):
     """Hybrid PIE of Algorithm 3 (Sec. 3.2), on the device.
 
     Phase 1 runs partial-transform sweeps on the central m x m window of the
@@ -139,6 +146,10 @@ def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_
     place; intensity is a device float32 [J][n][n] fftshift-layout tensor.
     Phase 2 uses the fast full-window transform where it applies
     (full_method "auto"; "dense" forces the contraction at m = n).
+    order: None (scan order), a device int32 permutation, or "random" for
+    a fresh permutation of the positions in every sweep (uniformly at
+    random without replacement, Sec. 4.3; numpy generator seeded with
+    order_seed).
     Returns the history [(phase, sweep, Phi, rel_change)].  The only host
     synchronisation is the read-back of the 4 statistics per sweep.
     """
@@ -146,6 +157,7 @@ def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_
     params = params or PieParams(batch=len(pos), norm=1)
     full_params = full_params or params
     history = []
+    rng = np.random.default_rng(order_seed)
     raise_nonfinite = True
     for phase, (mm, iters, tol, prm) in enumerate(((m, iters_pft, tol_pft, params),
                                                     (n, iters_full, tol_full, full_params))):
@@ -154,7 +166,12 @@ def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_
         amp = crop_amplitudes(intensity, mm)
         stats = torch.zeros(4, dtype=torch.float64, device=obj.device)
         for it in range(iters):
-            pie_sweep(obj, probe, scan, amp, prm, order=order, stats=stats)
+            ordr = order
+            if isinstance(order, str):
+                if order != "random":
+                    raise ValueError("order must be None, a permutation tensor or 'random'")
+                ordr = torch.from_numpy(rng.permutation(len(pos)).astype(np.int32)).to(obj.device)
+            pie_sweep(obj, probe, scan, amp, prm, order=ordr, stats=stats)
             st = stats.cpu().numpy()
             if raise_nonfinite and st[3] > 0:
                 raise FloatingPointError(f"phase {phase} sweep {it}: {int(st[3])} non-finite values")

@@ -264,14 +264,15 @@ def adjoint_descs(desc):
     return np.stack([d[:, 0], d[:, 1], d[:, 3], d[:, 2]], axis=1)
 
 
-def serpentine(k, step):
+def serpentine(k, step, by_rows=False):
     """k x k window corners, column by column: down the first column, up the
     second, down the third, ... (the scan of the non-blind experiments,
-    Sec. 4.2), as (row, col) offsets [k*k][2]."""
+    Sec. 4.2); by_rows: along the first row to the right, back along the
+    second, ... (the blind experiments), as (row, col) offsets [k*k][2]."""
     pos = []
-    for ix in range(k):
-        rows = range(k) if ix % 2 == 0 else range(k - 1, -1, -1)
-        pos += [(step * iy, step * ix) for iy in rows]
+    for a in range(k):
+        seq = range(k) if a % 2 == 0 else range(k - 1, -1, -1)
+        pos += [(step * a, step * b) if by_rows else (step * b, step * a) for b in seq]
     return np.asarray(pos, dtype=np.int32)
 
 
@@ -317,4 +318,32 @@ def masked_field(seed=6, field=16384, m=128, coarse=1024, sigma_f=24.0, amp_posi
     amp = masked_field_amplitudes(obj, probe, sel, m, field)
     init = random_init(rs[4], field, field) if with_init else None
     return dict(obj=obj, probe=probe, pos=pos, amp=amp, m=m, period=field, init=init)
+
+
+def circular_probe(n, radius, sigma=1e6):
+    """Circular illumination window of the blind experiments (Sec. 4.3): the
+    Gaussian exp(-r^2 / 2 sigma^2) inside a circle of `radius` px (sigma =
+    1e6: flat), zero outside."""
+    r2 = _radius2(n)
+    return ((r2 <= radius * radius) * np.exp(-r2 / (2.0 * sigma * sigma))).astype(np.complex64)
+
+
+def blind_circular(seed=7, n=128, radius=58.0, shift=50, grid=4, m=32):
+    """Blind ePIE with circular windows (Sec. 4.3), scaled so the full
+    window fits the full-resolution phase: 4 x 4 windows of n = 128 with a
+    flat circular probe of radius 58 shifted by 50 px (about the paper's
+    radius / shift ratio 175 / 150 and 50 % overlap), row-wise serpentine
+    scan, object padded to cover every window (3 * 50 + 128 = 278 px),
+    amplitude U[0.8, 1] with phase blobs in [-pi/2, pi/2], noise-free data;
+    initial object as Sec. 4.1.2, initial probe a flat circle of 0.8 times
+    the radius.  PFT window m."""
+    rs = streams(seed)
+    size = shift * (grid - 1) + n
+    obj = blob_object(rs[0], size, size)
+    probe = circular_probe(n, radius)
+    pos = serpentine(grid, shift, by_rows=True)
+    inten = intensities(obj, probe, pos)
+    init = random_init(rs[4], size, size)
+    probe0 = circular_probe(n, 0.8 * radius)
+    return dict(obj=obj, probe=probe, pos=pos, intensity=inten, m=m, init=init, probe_init=probe0)
 
