@@ -19,6 +19,9 @@ pie   the Fourier-magnitude projection (Sec. 2.1, eq. (3)), the objective
       (eq. (4)), the PIE / ePIE sweep (eqs. (5)-(6)), the stopping rule
       (Sec. 4) and the hybrid driver (Sec. 3.2, Algorithm 3).
 loss  the amplitude loss and its gradient with respect to object and probe.
+polypft  the paper's polynomial PFT (Sec. 3.1, Algorithms 1-2; Appendix A,
+      Algorithms 4-5), with near-minimax Chebyshev coefficients in place of
+      the unavailable minimax database.
 
 Parity status: every function is pinned by the CPU tests (``-m "not gpu"``)
 except ``pie.hybrid_pie``, whose convergence behaviour the paper shows only
@@ -26,4 +29,4 @@ in figures: parity unpinned for the hybrid driver's reconstruction quality
 (its individual sweeps are pinned).
 """
 
-from . import pft, pie, loss  # noqa: F401
+from . import pft, pie, loss, polypft  # noqa: F401
