@@ -205,6 +205,26 @@ def epie_blind_rate(torch, pk, m, sweeps=10, warmup=2):
             "method": scan.plan.method}
 
 
+def poly_rate(torch, pk, batch=512, steps=5, warmup=2):
+    """The paper's polynomial PFT (m~ = p = 64: m = 128, eps = 1e-7, r = 13)
+    against the exact dense transform on the same 256^2 patches: time per
+    batch, and the polynomial result's relative L2 difference from the
+    exact one (whose own error against the FP64 oracle is reported by the
+    CPU-baseline leg)."""
+    n, m = 256, 128
+    poly = pk.PolyPlan(n, m, 64, 1e-7)
+    dense = pk.Plan(n, m)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    x = torch.randn(batch, n, n, dtype=torch.complex64, device="cuda", generator=g)
+    out = {"batch": batch, "n": n, "m": m, "p": 64, "eps": 1e-7, "r": poly.r}
+    for name, fn in (("poly", lambda: poly.forward(x)), ("exact_dense", lambda: dense.forward(x))):
+        ms = time_calls(torch, fn, steps, warmup)
+        out[name] = {"ms": ms, "patches_per_s": batch / (ms * 1e-3)}
+    yp, ye = poly.forward(x), dense.forward(x)
+    out["poly"]["rel_diff_vs_exact"] = float(torch.linalg.vector_norm(yp - ye) / torch.linalg.vector_norm(ye))
+    return out
+
+
 def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
     import workloads
     case = workloads.tiny_pie()
@@ -349,6 +369,7 @@ def main():
         extra["pie_masked_field_16384"] = masked_field_rate(torch, pk)
         extra["epie_blind_circular_m32"] = epie_blind_rate(torch, pk, 32)
         extra["epie_blind_circular_m128"] = epie_blind_rate(torch, pk, 128)
+        extra["poly_pft_vs_exact_256_m128"] = poly_rate(torch, pk)
         extra["pie_tiny_sequential"] = pie_tiny_rate(torch, pk, 1, 0)
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])

@@ -73,6 +73,7 @@ typedef enum {
 } pftpie_method;
 
 typedef struct pftpie_plan_s* pftpie_plan;
+typedef struct pftpie_poly_s* pftpie_poly;
 typedef struct pie_scan_s* pie_scan;
 
 const char* pftpie_status_string(pftpie_status s);
@@ -132,6 +133,37 @@ pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,
  * precision).  The candidates are those of the dense contraction (which
  * uneven batches use for every plan); best_ms times the dense form. */
 pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* best_ms);
+
+/* ------------------------------------------------------------------------ */
+/* The paper's polynomial PFT (Sec. 3.1, Algorithms 1-2; Appendix A,
+ * Algorithms 4-5), kept beside the exact transform for comparison of error
+ * and speed.  With n = p q, each q x q block of the window is contracted
+ * with B[j][l] = w_l (1 - 2j/q)^l on both axes, the p x p grid of each
+ * (l1, l2) plane is transformed (fast transform in LDS), and the kept
+ * coefficients t_c = c - floor(m/2) are the sums over (l1, l2) of the
+ * planes at (t1 mod p, t2 mod p) weighted by W[t][l] = (t/p)^l
+ * exp(-pi i t / p) per axis.  w: the interpolant of exp(i pi x) at the r
+ * Chebyshev points of [-xi, xi], xi(eps, r) the largest scope within eps
+ * (bisection in double), r the least with xi(eps, r) >= floor(m/2) / p
+ * (Algorithm 1); each coefficient is within (2 eps + eps^2) * sum |psi| of
+ * the exact one (plus FP32 rounding).
+ *
+ * pftpie_poly_create: p in {16, 32, 64, 128}, p | n, n / p <= 32,
+ *   1 <= m <= min(n, 128), 0 < eps < 1; PFTPIE_E_UNSUPPORTED when no
+ *   r <= 25 reaches eps.  Synchronous; allocates device tables.
+ * pftpie_poly_info: the chosen r and xi (either pointer may be NULL).
+ * pftpie_poly_workspace_size: bytes of device workspace for `batch`
+ *   patches (2 batch r^2 p^2 complex64: the expanded and transformed
+ *   planes); the caller owns it.
+ * pft2d_poly_forward: psi device complex64 [batch][n][n] -> y [batch][m][m]
+ *   (centred order, as pft2d_forward); psi, y and ws 8-byte aligned, psi
+ *   and y disjoint; enqueued on `stream`. */
+pftpie_status pftpie_poly_create(int32_t n, int32_t m, int32_t p, double eps, pftpie_poly* out);
+pftpie_status pftpie_poly_destroy(pftpie_poly poly);
+pftpie_status pftpie_poly_info(pftpie_poly poly, int32_t* r, double* xi);
+pftpie_status pftpie_poly_workspace_size(pftpie_poly poly, int64_t batch, size_t* bytes);
+pftpie_status pft2d_poly_forward(pftpie_poly poly, const void* psi, void* y, int64_t batch, void* ws,
+                                 size_t ws_bytes, void* stream);
 
 /* Forward: y_b = F_m psi_b F_m^T for b < batch.
  *   psi: device complex64 [batch][n][n]; y: device complex64 [batch][m][m].

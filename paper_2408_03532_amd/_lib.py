@@ -44,6 +44,11 @@ SIGNATURES = {
     "pftpie_plan_method": (i32, [c_plan, ctypes.POINTER(i32)]),
     "pftpie_plan_create_period": (i32, [i32, i32, i32, i32, i32, ctypes.POINTER(c_plan)]),
     "pftpie_plan_period": (i32, [c_plan, ctypes.POINTER(i32)]),
+    "pftpie_poly_create": (i32, [i32, i32, i32, ctypes.c_double, ctypes.POINTER(c_plan)]),
+    "pftpie_poly_destroy": (i32, [c_plan]),
+    "pftpie_poly_info": (i32, [c_plan, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+    "pftpie_poly_workspace_size": (i32, [c_plan, i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "pft2d_poly_forward": (i32, [c_plan, vp, vp, i64, vp, ctypes.c_size_t, vp]),
     "pftpie_plan_destroy": (i32, [c_plan]),
     "pftpie_plan_info": (i32, [c_plan, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
     "pftpie_plan_autotune": (i32, [c_plan, i64, ctypes.POINTER(ctypes.c_double)]),

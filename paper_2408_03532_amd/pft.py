@@ -219,3 +219,58 @@ class Group:
         _lib.call("pft2d_group_run", self.handle, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                   _stream_ptr(inp))
         return out
+
+
+class PolyPlan:
+    """The paper's polynomial partial Fourier transform (Sec. 3.1,
+    Algorithms 1-2; Appendix A, Algorithms 4-5) for n x n patches, crop m,
+    divisor p and tolerance eps, beside the exact transform for comparison.
+    ``r`` and ``xi`` are the chosen number of polynomial terms and scope."""
+
+    def __init__(self, n, m, p, eps, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else
+                           torch.device(device).index or 0)
+        self.n, self.m, self.p, self.eps, self.device = int(n), int(m), int(p), float(eps), dev
+        h = _lib.c_plan()
+        with torch.cuda.device(dev):
+            _lib.call("pftpie_poly_create", self.n, self.m, self.p, self.eps, ctypes.byref(h))
+        self.handle = h
+        r, xi = ctypes.c_int32(), ctypes.c_double()
+        _lib.call("pftpie_poly_info", self.handle, ctypes.byref(r), ctypes.byref(xi))
+        self.r, self.xi = r.value, xi.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().pftpie_poly_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, batch):
+        nb = ctypes.c_size_t()
+        _lib.call("pftpie_poly_workspace_size", self.handle, int(batch), ctypes.byref(nb))
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def forward(self, psi, out=None):
+        """psi: complex64 [..., n, n] -> approximate centred [..., m, m]."""
+        _require(psi, "psi")
+        if psi.shape[-2:] != (self.n, self.n):
+            raise ValueError(f"psi must end in ({self.n}, {self.n})")
+        lead = psi.shape[:-2]
+        if out is None:
+            out = torch.empty(lead + (self.m, self.m), dtype=torch.complex64, device=psi.device)
+        _require(out, "out")
+        batch = psi.numel() // (self.n * self.n)
+        ws = self.workspace(batch)
+        _lib.call("pft2d_poly_forward", self.handle, ctypes.c_void_p(psi.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), batch, ctypes.c_void_p(ws.data_ptr()),
+                  ctypes.c_size_t(ws.numel()), _stream_ptr(psi))
+        return out
+

@@ -100,3 +100,18 @@ def test_python_layer_reports_missing_device_cleanly():
         pytest.skip("a GPU is visible")
     with pytest.raises(Exception):
         pk.Plan(32, 16)
+
+
+@pytest.mark.parametrize("n,m,p,eps,status,msg", [
+    (256, 128, 48, 1e-7, 2, b"p must be 16, 32, 64 or 128"),
+    (250, 64, 64, 1e-7, 1, b"p must divide n"),
+    (2048, 64, 32, 1e-7, 2, b"n / p above 32"),
+    (256, 128, 64, 0.0, 1, b"0 < eps < 1"),
+    (256, 128, 16, 1e-12, 2, b"no r <= 25"),   # m/2 / p = 4 needs more terms than 25
+])
+def test_poly_create_rejected_on_the_host(n, m, p, eps, status, msg):
+    L = pk.lib()
+    h = ctypes.c_void_p(123)
+    assert L.pftpie_poly_create(n, m, p, eps, ctypes.byref(h)) == status
+    assert h.value is None
+    assert msg in L.pftpie_last_error()
