@@ -16,9 +16,11 @@
 
 namespace pftpie {
 
+// n = 128: the block takes most of the LDS, one workgroup per compute
+// unit, so it brings four waves per SIMD itself to hide LDS latency.
 template <class G>
 constexpr int fft_threads() {
-  return G::N >= 64 ? 256 : (G::N == 32 ? 128 : 64);
+  return G::N >= 128 ? 1024 : (G::N == 64 ? 256 : (G::N == 32 ? 128 : 64));
 }
 template <class G>
 constexpr size_t fft_lds_bytes() {
@@ -115,8 +117,8 @@ __global__ __launch_bounds__(fft_threads<G>()) void k_pie_fft(PieArgs a, int c0)
   extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* buf = sm + G::N;
-  __shared__ double red_phi[4];
-  __shared__ float red_max[2][4];
+  __shared__ double red_phi[16];
+  __shared__ float red_max[2][16];
   constexpr int N = G::N;
   load_twiddles(tw, a.fft_tw, N);
   __syncthreads();
