@@ -290,7 +290,9 @@ struct DeltaSink {
   }
 };
 
-template <class PR, int MT, bool SINGLE>
+// K2 > 1 (FP32, long windows): each wave takes K2 neighbouring column tiles
+// so the FT table streams once per K2 tiles.
+template <class PR, int MT, bool SINGLE, int K2 = 1>
 __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
   const int q = blockIdx.x;
   bool valid;
@@ -307,10 +309,22 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
     }
     UpdateSink sink{a.O, a.P, a.n, a.W, ps.x, ps.y, a.norm, a.probe_step, (int)valid, a.probe_pass,
                     a.inv_n2, a.beta, a.gamma, regP, regO};
-    for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+    if constexpr (K2 > 1) {
+      for (int gi = blockIdx.y * nw + w; gi * K2 < a.nb; gi += gridDim.y * nw)
+        adj_tiles_f32<MT, K2>(src, a.nb, T, gi * K2, sink);
+    } else {
+      for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw)
+        adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+    }
   } else {
     DeltaSink sink{a.dpsi + (size_t)q * a.n * a.n, a.n, a.inv_n2};
-    for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw) adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+    if constexpr (K2 > 1) {
+      for (int gi = blockIdx.y * nw + w; gi * K2 < a.nb; gi += gridDim.y * nw)
+        adj_tiles_f32<MT, K2>(src, a.nb, T, gi * K2, sink);
+    } else {
+      for (int kt2 = blockIdx.y * nw + w; kt2 < a.nb; kt2 += gridDim.y * nw)
+        adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
+    }
   }
 }
 
@@ -587,19 +601,31 @@ static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   else
     fwd_launch<PR, MT, false>(a, c0, cnt, st);
   // column tiles of the adjoint over a second grid dimension when the chunk
-  // alone leaves compute units idle
+  // alone leaves compute units idle; long FP32 windows take K2 column tiles
+  // per wave (the FT table then streams 1/K2 as often; K2 = 2 above 64
+  // kept coefficients, where four tiles' accumulators would spill)
+  constexpr bool kF32 = std::is_same<PR, PrecF32>::value;
+  constexpr int K2 = kF32 ? (MT <= 4 ? 4 : 2) : 1;
+  const bool tiles4 = kF32 && a.nb >= 128;
+  const int units = tiles4 ? (a.nb + K2 - 1) / K2 : a.nb;
   const int nw = adj_waves(a.nb);
-  const int per = (a.nb + nw - 1) / nw;
+  const int per = (units + nw - 1) / nw;
   int gy = 1;
   if ((long)cnt * nw < 4L * a.num_cu) {
     const long want = (4L * a.num_cu + (long)cnt * nw - 1) / ((long)cnt * nw);
     gy = (int)(want < per ? want : per);
   }
   dim3 grid(cnt, gy), block(64 * nw);
-  if (single)
+  if (tiles4) {
+    if (single)
+      hipLaunchKernelGGL((k_pie_adjoint<PR, MT, true, K2>), grid, block, 0, st, a, c0);
+    else
+      hipLaunchKernelGGL((k_pie_adjoint<PR, MT, false, K2>), grid, block, 0, st, a, c0);
+  } else if (single) {
     hipLaunchKernelGGL((k_pie_adjoint<PR, MT, true>), grid, block, 0, st, a, c0);
-  else
+  } else {
     hipLaunchKernelGGL((k_pie_adjoint<PR, MT, false>), grid, block, 0, st, a, c0);
+  }
 }
 
 template <int MT>

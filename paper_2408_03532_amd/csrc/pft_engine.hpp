@@ -339,6 +339,87 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Ta
   adj_stage2_f32<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
 }
 
+// FP32 adjoint for long windows: K2 neighbouring column tiles kt2_0 ..
+// kt2_0 + K2 - 1 per wave.  Stage 1 shares each coefficient chunk between
+// the K2 tiles; stage 2 fetches each FT block (k1t, c1t) once for all K2
+// tiles, so the table (megabytes when n is in the thousands, past the
+// caches) streams NB / K2 instead of NB times per patch.  Tiles at or past
+// NB are computed on the last tile's twiddles and not stored.
+template <int MT, int K2, class YSrc, class Sink, class Tab>
+__device__ __forceinline__ void adj_tiles_f32(const YSrc& ysrc, int NB, const Tab& FT, int kt2_0, Sink& sink) {
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+  f32x4 Sre[K2][MT], Sim[K2][MT];
+#pragma unroll
+  for (int u = 0; u < K2; ++u)
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      Sre[u][a] = zero4();
+      Sim[u][a] = zero4();
+    }
+  int kt[K2];
+#pragma unroll
+  for (int u = 0; u < K2; ++u) kt[u] = kt2_0 + u < NB ? kt2_0 + u : NB - 1;
+  // stage 1: S_u[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2]) for every tile u
+#pragma unroll
+  for (int kb = 0; kb < MT; ++kb) {
+    c4 y[MT], f[K2];
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) y[c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+#pragma unroll
+    for (int u = 0; u < K2; ++u) f[u] = FT.f32((size_t)kt[u] * MT + kb, lane);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int u = 0; u < K2; ++u) {
+        const float fr = f[u].v[s].x, fi = f[u].v[s].y;
+#pragma unroll
+        for (int c1t = 0; c1t < MT; ++c1t) {
+          Sre[u][c1t] = mfma4(y[c1t].v[s].x, fr, Sre[u][c1t]);
+          Sim[u][c1t] = mfma4(y[c1t].v[s].y, fr, Sim[u][c1t]);
+          Sre[u][c1t] = mfma4(y[c1t].v[s].y, fi, Sre[u][c1t]);
+          Sim[u][c1t] = mfma4(-y[c1t].v[s].x, fi, Sim[u][c1t]);
+        }
+      }
+  }
+  // stage 2: X_u[k1][k2] = sum_c1 conj(F[c1][k1]) S_u[c1][k2], one row tile
+  // at a time, the next block fetched while this one's products issue
+  c4 fb[2];
+  fb[0] = FT.f32(0, lane);
+  for (int k1t = 0; k1t < NB; ++k1t) {
+    f32x4 Xre[K2], Xim[K2];
+#pragma unroll
+    for (int u = 0; u < K2; ++u) {
+      Xre[u] = zero4();
+      Xim[u] = zero4();
+    }
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      const int cur = c1t & 1;
+      const int nk = c1t + 1 < MT ? k1t : (k1t + 1 < NB ? k1t + 1 : k1t);
+      const int nc = c1t + 1 < MT ? c1t + 1 : 0;
+      fb[cur ^ 1] = FT.f32((size_t)nk * MT + nc, lane);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float fr = fb[cur].v[i].x, fi = fb[cur].v[i].y;
+#pragma unroll
+        for (int u = 0; u < K2; ++u) {
+          const float sr = Sre[u][c1t][i], si = Sim[u][c1t][i];
+          Xre[u] = mfma4(fr, sr, Xre[u]);
+          Xim[u] = mfma4(fr, si, Xim[u]);
+          Xre[u] = mfma4(fi, si, Xre[u]);
+          Xim[u] = mfma4(-fi, sr, Xim[u]);
+        }
+      }
+    }
+    if constexpr ((MT & 1) != 0) fb[0] = fb[1];
+#pragma unroll
+    for (int u = 0; u < K2; ++u)
+      if (kt2_0 + u < NB) sink.template put<false>(k1t, kt2_0 + u, Xre[u], Xim[u]);
+  }
+}
+
 // FP32 adjoint, one whole patch per wave (MT <= 4): the m x m coefficients
 // stay in registers (128 at MT = 4) for every column tile kt2, so the wave
 // issues no memory loads between its output stores.
