@@ -21,6 +21,7 @@
 //   k_pie_reduce_max, k_pie_apply   maxima and the normalised updates.
 // Per sweep: k_pie_begin (object copy, ranks, clears) and the statistics
 // pair k_pie_stats_part / k_pie_stats_final (fixed-order sums).
+#include <atomic>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -560,6 +561,22 @@ static int ew_blocks(size_t work) {
 
 // forward split: WR row groups so a chunk keeps the compute units busy, as
 // long as the partial spectra fit the LDS (WR - 1 copies of MT x MT tiles)
+
+// Workgroups of Kernel at `threads` threads (a multiple of 64, at most 1024)
+// that one compute unit holds at once; the first query of each kernel and
+// block size asks the runtime, later ones read the cache.
+template <auto Kernel>
+static int blocks_per_cu(int threads) {
+  static std::atomic<int> cache[17];
+  const int w = threads >> 6;
+  int n = cache[w].load(std::memory_order_relaxed);
+  if (n == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, Kernel, threads, 0) != hipSuccess || n < 1) n = 1;
+    cache[w].store(n, std::memory_order_relaxed);
+  }
+  return n;
+}
+
 template <int MT>
 constexpr int pie_wr() {
   return MT <= 2 ? 4 : (MT <= 4 ? 2 : 1);
@@ -578,7 +595,7 @@ static void fwd_launch(const PieArgs& a, int c0, int cnt, hipStream_t st) {
     // long windows (>= 8 strips per row group, FP32, untracked): four strips
     // per pass share each twiddle block of the uncached table
     constexpr bool kRs = std::is_same<PR, PrecF32>::value && !TRACK;
-    if (kRs && exact && a.nb >= 8 * WR * a.splits)
+    if (kRs && exact && pie_fwd_rs(a.nb, WR, a.splits))
       hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK, true, kRs ? 4 : 1>), grid, block, 0, st, a, c0);
     else if (exact)
       hipLaunchKernelGGL((k_pie_forward<PR, MT, CT, WR, true, TRACK, true>), grid, block, 0, st, a, c0);
@@ -601,9 +618,10 @@ static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   else
     fwd_launch<PR, MT, false>(a, c0, cnt, st);
   // column tiles of the adjoint over a second grid dimension when the chunk
-  // alone leaves compute units idle; long FP32 windows take K2 column tiles
-  // per wave (the FT table then streams 1/K2 as often; K2 = 2 above 64
-  // kept coefficients, where four tiles' accumulators would spill)
+  // alone leaves compute units idle, balanced against the workgroups that
+  // fit on the chip at once; long FP32 windows take K2 column tiles per wave
+  // (the FT table then streams 1/K2 as often; K2 = 2 above 64 kept
+  // coefficients, where four tiles' accumulators would spill)
   constexpr bool kF32 = std::is_same<PR, PrecF32>::value;
   constexpr int K2 = kF32 ? (MT <= 4 ? 4 : 2) : 1;
   const bool tiles4 = kF32 && a.nb >= 128;
@@ -612,8 +630,14 @@ static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   const int per = (units + nw - 1) / nw;
   int gy = 1;
   if ((long)cnt * nw < 4L * a.num_cu) {
-    const long want = (4L * a.num_cu + (long)cnt * nw - 1) / ((long)cnt * nw);
-    gy = (int)(want < per ? want : per);
+    int occ;
+    if (tiles4)
+      occ = single ? blocks_per_cu<k_pie_adjoint<PR, MT, true, K2>>(64 * nw)
+                   : blocks_per_cu<k_pie_adjoint<PR, MT, false, K2>>(64 * nw);
+    else
+      occ = single ? blocks_per_cu<k_pie_adjoint<PR, MT, true>>(64 * nw)
+                   : blocks_per_cu<k_pie_adjoint<PR, MT, false>>(64 * nw);
+    gy = pie_balanced_y(cnt, units, nw, per, (long)a.num_cu * occ);
   }
   dim3 grid(cnt, gy), block(64 * nw);
   if (tiles4) {
@@ -626,6 +650,37 @@ static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   } else {
     hipLaunchKernelGGL((k_pie_adjoint<PR, MT, false>), grid, block, 0, st, a, c0);
   }
+}
+
+template <class PR, int MT>
+static int fwd_split_blocks(bool rs) {
+  constexpr int CT = (MT <= 2) ? MT : 2;
+  constexpr int WC = (MT + CT - 1) / CT;
+  constexpr int WR = pie_wr<MT>();
+  constexpr bool kF32 = std::is_same<PR, PrecF32>::value;
+  if (rs && kF32) return blocks_per_cu<k_pie_forward<PR, MT, CT, WR, true, false, true, kF32 ? 4 : 1>>(64 * WR * WC);
+  return blocks_per_cu<k_pie_forward<PR, MT, CT, WR, true, false, true>>(64 * WR * WC);
+}
+
+template <class PR>
+static int fwd_split_blocks_mt(int mt, bool rs) {
+  switch (mt) {
+    case 1: return fwd_split_blocks<PR, 1>(rs);
+    case 2: return fwd_split_blocks<PR, 2>(rs);
+    case 3: return fwd_split_blocks<PR, 3>(rs);
+    case 4: return fwd_split_blocks<PR, 4>(rs);
+    case 5: return fwd_split_blocks<PR, 5>(rs);
+    case 6: return fwd_split_blocks<PR, 6>(rs);
+    case 7: return fwd_split_blocks<PR, 7>(rs);
+    case 8: return fwd_split_blocks<PR, 8>(rs);
+    default: return 1;
+  }
+}
+
+int pie_fwd_split_blocks_per_cu(pftpie_precision prec, int mt, bool rs) {
+  if (prec == PFTPIE_SPLIT_BF16) return fwd_split_blocks_mt<PrecBF16>(mt, rs);
+  if (prec == PFTPIE_SPLIT_FP16) return fwd_split_blocks_mt<PrecF16>(mt, rs);
+  return fwd_split_blocks_mt<PrecF32>(mt, rs);
 }
 
 template <int MT>

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 #ifdef __HIPCC__
 #include "device_common.hpp"
@@ -67,21 +69,64 @@ constexpr int kStatBlocks = 512;
 inline int pie_ct(int mt) { return mt <= 2 ? mt : 2; }
 inline int pie_wc(int mt) { return (mt + pie_ct(mt) - 1) / pie_ct(mt); }
 inline int pie_wr_rt(int mt) { return mt <= 2 ? 4 : (mt <= 4 ? 2 : 1); }
-// Workgroups per position in the forward for chunks of `batch` positions:
-// few large windows split their row strips over more workgroups (partial
-// spectra summed by a projection kernel) until the chunk has about four
-// waves per compute unit, keeping at least one strip per row group, and
-// for long windows (nb >= 128) at least eight, so that passes of several
-// strips can share the twiddle blocks of the uncached table.
-inline int pie_row_splits(int nb, int mt, int batch, int num_cu) {
-  const long waves = (long)batch * pie_wc(mt) * pie_wr_rt(mt);
-  const long target = 4L * num_cu;
-  if (waves >= target) return 1;
-  long s = (target + waves - 1) / waves;
-  const long cap = nb >= 128 ? nb / (8 * pie_wr_rt(mt)) : nb / pie_wr_rt(mt);
-  if (s > cap) s = cap;
-  return s < 1 ? 1 : (int)s;
+// Long windows split over several workgroups pass four strips at a time over
+// each twiddle block when every row group keeps at least eight strips.
+inline bool pie_fwd_rs(int nb, int wr, int splits) { return splits > 1 && nb >= 8 * wr * splits; }
+
+// Workgroups per position in the forward for chunks of `batch` positions.
+// Few large windows split their row strips over several workgroups (partial
+// spectra summed by a projection kernel) while the chunk alone has fewer than
+// four waves per compute unit.  The split count s minimises (rounds of
+// co-resident workgroups) x (strips per row group), with `slots_plain` /
+// `slots_rs` workgroups of the one-strip / four-strip kernels resident on
+// the chip at once and strips counted in whole passes of four where those
+// apply (rs_ok: FP32, whole tiles); ties keep the smaller s.  Every row group
+// keeps at least one strip, and on long windows (nb >= 128) at least eight.
+inline int pie_row_splits(int nb, int mt, int batch, int num_cu, long slots_plain, long slots_rs, bool rs_ok) {
+  const int wr = pie_wr_rt(mt);
+  const long waves = (long)batch * pie_wc(mt) * wr;
+  if (waves >= 4L * num_cu) return 1;
+  long cap = nb >= 128 ? nb / (8 * wr) : nb / wr;
+  if (cap < 1) cap = 1;
+  int best = 1;
+  long best_cost = -1;
+  for (int s = 1; s <= cap; ++s) {
+    const bool rs = rs_ok && pie_fwd_rs(nb, wr, s);
+    const long slots = std::max(1L, rs ? slots_rs : slots_plain);
+    const long rounds = ((long)batch * s + slots - 1) / slots;
+    long strips = (nb + (long)wr * s - 1) / ((long)wr * s);
+    if (rs) strips = (strips + 3) / 4 * 4;
+    const long cost = rounds * strips;
+    if (best_cost < 0 || cost < best_cost) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
+
+// The least g in [1, gmax] minimising (rounds of co-resident workgroups,
+// `slots` at once) x (work units per wave) for `items` x g workgroups of
+// `nw` waves sharing `units` units of work per item.
+inline int pie_balanced_y(long items, long units, int nw, int gmax, long slots) {
+  slots = std::max(1L, slots);
+  int best = 1;
+  long best_cost = -1;
+  for (int g = 1; g <= gmax; ++g) {
+    const long rounds = (items * g + slots - 1) / slots;
+    const long per = (units + (long)g * nw - 1) / ((long)g * nw);
+    const long cost = rounds * per;
+    if (best_cost < 0 || cost < best_cost) {
+      best = g;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+// Split-forward workgroups of the one-strip (rs = false) or four-strip
+// kernel that one compute unit holds at once (HIP occupancy query).
+int pie_fwd_split_blocks_per_cu(pftpie_precision prec, int mt, bool rs);
 
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);

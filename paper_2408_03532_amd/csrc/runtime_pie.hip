@@ -32,7 +32,14 @@ PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
     return o;
   };
   L.R = take((size_t)batch * p->m * p->m * 8);
-  L.splits = p->method == PFTPIE_METHOD_FFT ? 1 : pie_row_splits(p->nb, p->mt, batch, p->num_cu);
+  if (p->method == PFTPIE_METHOD_FFT) {
+    L.splits = 1;
+  } else {
+    const long plain = (long)p->num_cu * pie_fwd_split_blocks_per_cu(p->prec, p->mt, false);
+    const long rs = (long)p->num_cu * pie_fwd_split_blocks_per_cu(p->prec, p->mt, true);
+    L.splits = pie_row_splits(p->nb, p->mt, batch, p->num_cu, plain, rs,
+                              p->prec == PFTPIE_FP32 && p->n % 16 == 0);
+  }
   L.part = L.splits > 1 ? take((size_t)batch * L.splits * p->m * p->m * 8) : SIZE_MAX;
   L.dpsi = multi ? take((size_t)batch * nn * 8) : SIZE_MAX;
   L.phi = take((size_t)s->J * 4 * 8);
