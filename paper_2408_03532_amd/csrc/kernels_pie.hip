@@ -377,29 +377,50 @@ __global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int
 // numO and D with the tile's maximum of D.
 __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, int cnt) {
   __shared__ double sh[4];
+  // the tile's cover-list entries of this chunk, staged 256 at a time: slot
+  // in the chunk and window corner (entries outside the chunk get slot -1)
+  __shared__ int eq[256];
+  __shared__ int2 epos[256];
   const int tile = blockIdx.x;
   const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
   const int py = a.bb_r0 + ty * 16 + (threadIdx.x >> 4);
   const int px = a.bb_c0 + tx * 16 + (threadIdx.x & 15);
   const bool inside = (py < a.bb_r0 + a.bb_h) && (px < a.bb_c0 + a.bb_w);
   const size_t nn = (size_t)a.n * a.n;
+  if (a.norm && tile == 0 && threadIdx.x == 0) {
+    // the maxima that k_pie_reduce_max collects next start from zero
+    a.maxes[0] = 0.0;
+    a.maxes[1] = 0.0;
+  }
   float2 acc = make_float2(0.f, 0.f);
   double D = 0.0;
   const int e0 = a.tile_ptr[tile], e1 = a.tile_ptr[tile + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int j = a.tile_pos[e];
-    const int q = a.rank[j] - c0;
-    if (q < 0 || q >= cnt) continue;
-    const int2 ps = a.pos[j];
-    const int dy = py - ps.x, dx = px - ps.y;
-    if (!inside || dy < 0 || dy >= a.n || dx < 0 || dx >= a.n) continue;
-    const size_t k = (size_t)dy * a.n + dx;
-    const float2 p = a.P[k];
-    const float2 d = a.dpsi[(size_t)q * nn + k];
-    const float2 v = cmulc(p, d);
-    acc.x += v.x;
-    acc.y += v.y;
-    D += (double)p.x * p.x + (double)p.y * p.y;
+  for (int eb = e0; eb < e1; eb += 256) {
+    const int ne = (e1 - eb < 256) ? e1 - eb : 256;
+    __syncthreads();
+    if ((int)threadIdx.x < ne) {
+      const int j = a.tile_pos[eb + threadIdx.x];
+      const int q = a.rank[j] - c0;
+      eq[threadIdx.x] = (q >= 0 && q < cnt) ? q : -1;
+      epos[threadIdx.x] = a.pos[j];
+    }
+    __syncthreads();
+    // list order, as the entries were sorted: the sums are independent of
+    // how the list is staged
+    for (int i = 0; i < ne; ++i) {
+      const int q = eq[i];
+      if (q < 0) continue;
+      const int2 ps = epos[i];
+      const int dy = py - ps.x, dx = px - ps.y;
+      if (!inside || dy < 0 || dy >= a.n || dx < 0 || dx >= a.n) continue;
+      const size_t k = (size_t)dy * a.n + dx;
+      const float2 p = a.P[k];
+      const float2 d = a.dpsi[(size_t)q * nn + k];
+      const float2 v = cmulc(p, d);
+      acc.x += v.x;
+      acc.y += v.y;
+      D += (double)p.x * p.x + (double)p.y * p.y;
+    }
   }
   const size_t o = (size_t)py * a.W + px;
   if (!a.norm) {
@@ -417,19 +438,26 @@ __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, in
   if (threadIdx.x == 0) a.maxpart[tile] = mx;
 }
 
-// maxes[0] = max D over the tile maxima, maxes[1] = max E over the probe blocks.
-__global__ __launch_bounds__(1024) void k_pie_reduce_max(PieArgs a, int nprobe_blocks) {
-  __shared__ double sh[16];
+// maxes[0] = max D over the tile maxima, maxes[1] = max E over the probe
+// blocks (both cleared by k_pie_object_gather).  The maxima are of
+// non-negative doubles, whose bit patterns order as unsigned integers, so
+// the blocks combine them with integer atomic maxima: exact, and the same
+// in any order.
+__global__ __launch_bounds__(256) void k_pie_reduce_max(PieArgs a, int nprobe_blocks) {
+  __shared__ double sh[4];
   const int ntiles = a.tiles_x * a.tiles_y;
   double mD = 0.0, mE = 0.0;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) mD = fmax(mD, a.maxpart[t]);
-  for (int t = threadIdx.x; t < nprobe_blocks; t += blockDim.x) mE = fmax(mE, a.maxpart[ntiles + t]);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
+    mD = fmax(mD, a.maxpart[t]);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nprobe_blocks; t += gridDim.x * blockDim.x)
+    mE = fmax(mE, a.maxpart[ntiles + t]);
   mD = block_max(mD, sh);
   __syncthreads();
   mE = block_max(mE, sh);
   if (threadIdx.x == 0) {
-    a.maxes[0] = mD;
-    a.maxes[1] = mE;
+    unsigned long long* bits = reinterpret_cast<unsigned long long*>(a.maxes);
+    if (mD > 0.0) atomicMax(&bits[0], (unsigned long long)__double_as_longlong(mD));
+    if (mE > 0.0) atomicMax(&bits[1], (unsigned long long)__double_as_longlong(mE));
   }
 }
 
@@ -522,18 +550,26 @@ __global__ __launch_bounds__(256) void k_pie_stats_part(PieArgs a) {
 }
 
 // stats = {Phi, ||dO||^2, ||O||^2, non-finite}: one wave, fixed order.
-__global__ __launch_bounds__(64) void k_pie_stats_final(PieArgs a, int nblocks) {
+__global__ __launch_bounds__(1024) void k_pie_stats_final(PieArgs a, int nblocks) {
+  __shared__ double sh[4][16];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const size_t np = (size_t)a.J * 4;
-  for (size_t t = threadIdx.x; t < np; t += 64) v[0] += a.phi_part[t];
-  for (int b = threadIdx.x; b < nblocks; b += 64)
+  for (size_t t = threadIdx.x; t < np; t += blockDim.x) v[0] += a.phi_part[t];
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int c = 0; c < 3; ++c) v[c + 1] += a.red[(size_t)b * 3 + c];
   for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 4; ++c) sh[c][w] = v[c];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    a.stats[0] = v[0] / ((double)a.J * a.period * a.period);
-    a.stats[1] = v[1];
-    a.stats[2] = v[2];
-    a.stats[3] = v[3];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nw; ++k)
+      for (int c = 0; c < 4; ++c) s[c] += sh[c][k];
+    a.stats[0] = s[0] / ((double)a.J * a.period * a.period);
+    a.stats[1] = s[1];
+    a.stats[2] = s[2];
+    a.stats[3] = s[3];
   }
 }
 
@@ -737,14 +773,19 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
     if (cnt == 1) continue;  // updated in place
     if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt);
     hipLaunchKernelGGL(k_pie_object_gather, dim3(ntiles), dim3(256), 0, st, a, c0, cnt);
-    if (a.norm) hipLaunchKernelGGL(k_pie_reduce_max, dim3(1), dim3(1024), 0, st, a, a.probe_step ? pblocks : 0);
+    if (a.norm) {
+      const int items = ntiles > pblocks ? ntiles : pblocks;
+      int rb = (items + 255) / 256;
+      if (rb > 1024) rb = 1024;
+      hipLaunchKernelGGL(k_pie_reduce_max, dim3(rb), dim3(256), 0, st, a, a.probe_step ? pblocks : 0);
+    }
     if (a.norm || a.probe_step) {
       const size_t area = a.norm ? (size_t)a.bb_h * a.bb_w : (size_t)a.n * a.n;
       hipLaunchKernelGGL(k_pie_apply, dim3(ew_blocks(area)), dim3(256), 0, st, a, a.norm);
     }
   }
   hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(64), 0, st, a, kStatBlocks);
+  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks);
   return hipGetLastError();
 }
 
