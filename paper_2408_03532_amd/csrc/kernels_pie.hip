@@ -351,17 +351,36 @@ __global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int
   if (k < nn) {
     const int k1 = (int)(k / a.n), k2 = (int)(k % a.n);
     float2 acc = make_float2(0.f, 0.f);
-    for (int q = 0; q < cnt; ++q) {
-      bool valid;
-      const int j = pos_index(a.order, a.J, c0, q, &valid);
-      if (!valid) continue;
-      const int2 ps = a.pos[j];
-      const float2 o = a.O[(size_t)(ps.x + k1) * a.W + ps.y + k2];
-      const float2 d = a.dpsi[(size_t)q * nn + k];
-      const float2 v = cmulc(o, d);
-      acc.x += v.x;
-      acc.y += v.y;
-      e += (double)o.x * o.x + (double)o.y * o.y;
+    // U positions at a time: the loads of the group's valid entries all
+    // issue before any is used; contributions are added in chunk order
+    constexpr int U = 8;
+    for (int qb = 0; qb < cnt; qb += U) {
+      float2 ov[U], dv[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qb + u;
+        bool valid = false;
+        int2 ps = make_int2(0, 0);
+        if (q < cnt) {
+          const int j = pos_index(a.order, a.J, c0, q, &valid);
+          ps = a.pos[j];
+        }
+        ok[u] = valid;
+        ov[u] = dv[u] = make_float2(0.f, 0.f);
+        if (valid) {
+          ov[u] = a.O[(size_t)(ps.x + k1) * a.W + ps.y + k2];
+          dv[u] = a.dpsi[(size_t)q * nn + k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        const float2 v = cmulc(ov[u], dv[u]);
+        acc.x += v.x;
+        acc.y += v.y;
+        e += (double)ov[u].x * ov[u].x + (double)ov[u].y * ov[u].y;
+      }
     }
     a.numP[k] = acc;
     if (a.norm) a.E[k] = e;
@@ -377,10 +396,6 @@ __global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int
 // numO and D with the tile's maximum of D.
 __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, int cnt) {
   __shared__ double sh[4];
-  // the tile's cover-list entries of this chunk, staged 256 at a time: slot
-  // in the chunk and window corner (entries outside the chunk get slot -1)
-  __shared__ int eq[256];
-  __shared__ int2 epos[256];
   const int tile = blockIdx.x;
   const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
   const int py = a.bb_r0 + ty * 16 + (threadIdx.x >> 4);
@@ -395,31 +410,44 @@ __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, in
   float2 acc = make_float2(0.f, 0.f);
   double D = 0.0;
   const int e0 = a.tile_ptr[tile], e1 = a.tile_ptr[tile + 1];
-  for (int eb = e0; eb < e1; eb += 256) {
-    const int ne = (e1 - eb < 256) ? e1 - eb : 256;
-    __syncthreads();
-    if ((int)threadIdx.x < ne) {
-      const int j = a.tile_pos[eb + threadIdx.x];
-      const int q = a.rank[j] - c0;
-      eq[threadIdx.x] = (q >= 0 && q < cnt) ? q : -1;
-      epos[threadIdx.x] = a.pos[j];
+  // U cover-list entries at a time: the loads of the group's entries that
+  // reach this pixel are all issued before any is used, then the
+  // contributions are added in list order
+  constexpr int U = 8;
+  for (int eb = e0; eb < e1; eb += U) {
+    int qv[U];
+    int2 cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      qv[u] = -1;
+      cv[u] = make_int2(0, 0);
+      if (eb + u < e1) {
+        const int j = a.tile_pos[eb + u];
+        const int q = a.rank[j] - c0;
+        if (q >= 0 && q < cnt) qv[u] = q;
+        cv[u] = a.pos[j];
+      }
     }
-    __syncthreads();
-    // list order, as the entries were sorted: the sums are independent of
-    // how the list is staged
-    for (int i = 0; i < ne; ++i) {
-      const int q = eq[i];
-      if (q < 0) continue;
-      const int2 ps = epos[i];
-      const int dy = py - ps.x, dx = px - ps.y;
-      if (!inside || dy < 0 || dy >= a.n || dx < 0 || dx >= a.n) continue;
-      const size_t k = (size_t)dy * a.n + dx;
-      const float2 p = a.P[k];
-      const float2 d = a.dpsi[(size_t)q * nn + k];
-      const float2 v = cmulc(p, d);
+    float2 pv[U], dv[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int dy = py - cv[u].x, dx = px - cv[u].y;
+      ok[u] = inside && qv[u] >= 0 && dy >= 0 && dy < a.n && dx >= 0 && dx < a.n;
+      pv[u] = dv[u] = make_float2(0.f, 0.f);
+      if (ok[u]) {
+        const size_t k = (size_t)dy * a.n + dx;
+        pv[u] = a.P[k];
+        dv[u] = a.dpsi[(size_t)qv[u] * nn + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      const float2 v = cmulc(pv[u], dv[u]);
       acc.x += v.x;
       acc.y += v.y;
-      D += (double)p.x * p.x + (double)p.y * p.y;
+      D += (double)pv[u].x * pv[u].x + (double)pv[u].y * pv[u].y;
     }
   }
   const size_t o = (size_t)py * a.W + px;
@@ -464,10 +492,10 @@ __global__ __launch_bounds__(256) void k_pie_reduce_max(PieArgs a, int nprobe_bl
 // Normalised object update over the bounding box and the probe update.
 __global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
   if (object_part) {
-    const size_t total = (size_t)a.bb_h * a.bb_w;
     const double regO = a.alpha * a.maxes[0];
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-      const int rr = (int)(t / a.bb_w), cc = (int)(t % a.bb_w);
+    // rows of the bounding box over blockIdx.y, columns over blockIdx.x
+    for (int rr = blockIdx.y; rr < a.bb_h; rr += gridDim.y)
+    for (int cc = blockIdx.x * blockDim.x + threadIdx.x; cc < a.bb_w; cc += gridDim.x * blockDim.x) {
       const size_t o = (size_t)(a.bb_r0 + rr) * a.W + a.bb_c0 + cc;
       const double d = a.D[o];
       if (d > 0.0) {
@@ -481,7 +509,9 @@ __global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
   if (a.probe_step) {
     const size_t nn = (size_t)a.n * a.n;
     const double regP = a.alpha * a.maxes[1];
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < nn; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t nthreads = (size_t)gridDim.x * gridDim.y * blockDim.x;
+    const size_t t0 = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+    for (size_t t = t0; t < nn; t += nthreads) {
       const float2 num = a.numP[t];
       float sc = a.gamma;
       if (a.norm) {
@@ -780,8 +810,18 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
       hipLaunchKernelGGL(k_pie_reduce_max, dim3(rb), dim3(256), 0, st, a, a.probe_step ? pblocks : 0);
     }
     if (a.norm || a.probe_step) {
-      const size_t area = a.norm ? (size_t)a.bb_h * a.bb_w : (size_t)a.n * a.n;
-      hipLaunchKernelGGL(k_pie_apply, dim3(ew_blocks(area)), dim3(256), 0, st, a, a.norm);
+      // object part: columns of the bounding box over x, rows over y; the
+      // probe part runs over the flattened grid
+      int gx = 1, gy = 1;
+      if (a.norm) {
+        gx = (a.bb_w + 255) / 256;
+        gy = a.bb_h;
+        if (gx > 64) gx = 64;
+        if (gy > 4096 / gx) gy = 4096 / gx;
+      }
+      const int pb = a.probe_step ? ew_blocks((size_t)a.n * a.n) : 1;
+      if (gx * gy < pb) gy = (pb + gx - 1) / gx;
+      hipLaunchKernelGGL(k_pie_apply, dim3(gx, gy), dim3(256), 0, st, a, a.norm);
     }
   }
   hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);

@@ -62,7 +62,7 @@ struct PieArgs {
   double* stats;    // [4]
 };
 
-constexpr int kStatBlocks = 512;
+constexpr int kStatBlocks = 2048;
 
 // Forward work split of the dense sweep for MT = ceil(m/16) tiles per axis:
 // CT column tiles per wave, WC column groups, WR row groups per workgroup.
