@@ -305,9 +305,10 @@ static hipError_t adj_mt(const pftpie_plan_s* p, const float2* y, float2* psi, i
     const int64_t items = batch * p->nb;
     const bool exact = (p->m % 16 == 0) && ((uintptr_t)y % 16 == 0);
     if constexpr (MT <= 4) {
-      // (two stage-2 row tiles per step: four would spill at m = 64)
+      // (one stage-2 row tile per step: the three accumulator sets of two
+      // would spill at m = 64)
       if (p->prec == PFTPIE_FP32 && exact && p->adj_patch)
-        return launch_lds(k_adjoint_patch_f32_lds<MT, 2>, p, p->ft_bytes, batch, st, y, psi, p->ft, batch, 512);
+        return launch_lds(k_adjoint_patch_f32_lds<MT, 1>, p, p->ft_bytes, batch, st, y, psi, p->ft, batch, 512);
       if (p->prec != PFTPIE_FP32 && exact && p->adj_patch && p->n % 16 == 0 && (uintptr_t)psi % 16 == 0)
         return p->prec == PFTPIE_SPLIT_BF16
                    ? launch_lds(k_adjoint_patch_lds<PrecBF16, MT>, p, p->ft_bytes, batch, st, y, psi, p->ft, batch,

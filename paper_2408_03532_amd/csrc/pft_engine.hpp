@@ -3,8 +3,7 @@
 // Forward   Y = F T,       T = psi F^T       (Appendix A, 2-D DFT restricted
 //                                             to the kept window)
 // Adjoint   X = F^H S,     S = Y conj(F)^T   (exact adjoint, no scaling)
-// with F = F_m the m x n partial DFT matrix.  Complex products are four real
-// MFMA products; the negated operand is formed in a register.
+// with F = F_m the m x n partial DFT matrix.
 //
 // Forward: one wave owns CT column tiles (16 output columns each) of Y for
 // one patch.  It streams psi in 16-row strips; for each strip it contracts
@@ -54,11 +53,114 @@ struct PlainSrc {
   }
 };
 
-// Forward engine.  NB = ceil(n/16) row strips / column blocks.  FA holds
-// ctiles x NB blocks.  c2t0: first column tile this wave owns.
+// Complex products in three real MFMA products (Gauss): for data a + ib and
+// twiddle c + id,
+//   k1 = a (c + d),  k2 = d (a + b),  k3 = c (b - a),
+//   re = k1 - k2,    im = k1 + k3,
+// each k accumulated over the contraction in its own registers.  The two
+// data-side sums are formed once per data element (shared by every twiddle
+// tile that element meets), c + d once per twiddle element.
+
+// Forward engine, three products per complex product (output blocks of up
+// to 8 tiles per wave, whose three accumulator sets fit the registers).
 template <int MT, int CT, class Src, class Tab>
-__device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
-                                         f32x4 (&Yim)[MT][CT], int strip0 = 0, int sstep = 1) {
+__device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
+                                         f32x4 (&Yim)[MT][CT], int strip0, int sstep) {
+  const int lane = lane_id();
+  const int r16 = lane & 15, g = lane >> 4;
+  // Yre accumulates k1, Yim k3, Y2 k2 of the stage-2 products
+  f32x4 Y2[MT][CT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      Yre[a][b] = zero4();
+      Yim[a][b] = zero4();
+      Y2[a][b] = zero4();
+    }
+  for (int strip = strip0; strip < NB; strip += sstep) {
+    const int row = strip * 16 + r16;
+    f32x4 T1[CT], T2[CT], T3[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      T1[ct] = zero4();
+      T2[ct] = zero4();
+      T3[ct] = zero4();
+    }
+    // stage 1 over column blocks (data psi, twiddle F^T), two register sets
+    // in ping-pong so the loads of one block are in flight while the other
+    // block's products issue
+    auto stage1 = [&](const c4& a, const c4(&f)[CT]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float ar = a.v[s].x, ai = a.v[s].y;
+        const float sab = ar + ai, dba = ai - ar;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const float fr = f[ct].v[s].x, fi = f[ct].v[s].y;
+          T1[ct] = mfma4(ar, fr + fi, T1[ct]);
+          T2[ct] = mfma4(sab, fi, T2[ct]);
+          T3[ct] = mfma4(dba, fr, T3[ct]);
+        }
+      }
+    };
+    auto fetch = [&](int kb, c4& a, c4(&f)[CT]) {
+      a = src.load(row, kb * 16 + 4 * g);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) f[ct] = FA.f32((size_t)(c2t0 + ct) * NB + kb, lane);
+    };
+    c4 a0, a1, f0[CT], f1[CT];
+    fetch(0, a0, f0);
+    int kb = 0;
+    for (; kb + 1 < NB; kb += 2) {
+      fetch(kb + 1, a1, f1);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a0, f0);
+      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a1, f1);
+    }
+    if (kb < NB) stage1(a0, f0);
+    // T strip = a + ib with a = k1 - k2, b = k1 + k3; stage 2 takes T as the
+    // data side: a in T1, a + b in T2, b - a in T3
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const f32x4 tr = T1[ct] - T2[ct], ti = T1[ct] + T3[ct];
+      T1[ct] = tr;
+      T2[ct] = tr + ti;
+      T3[ct] = ti - tr;
+    }
+    // stage 2: Y[c1 tile][own tiles] += F[c1 tile, strip] * T[strip, own tiles]
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      c4 fb = FA.f32((size_t)c1t * NB + strip, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float fr = fb.v[i].x, fi = fb.v[i].y, cd = fr + fi;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          Yre[c1t][ct] = mfma4(cd, T1[ct][i], Yre[c1t][ct]);
+          Y2[c1t][ct] = mfma4(fi, T2[ct][i], Y2[c1t][ct]);
+          Yim[c1t][ct] = mfma4(fr, T3[ct][i], Yim[c1t][ct]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const f32x4 k1 = Yre[a][b];
+      Yre[a][b] = k1 - Y2[a][b];
+      Yim[a][b] = k1 + Yim[a][b];
+    }
+}
+
+// Forward engine, four products per complex product (the negated operand
+// formed in a register), for wider output blocks.
+template <int MT, int CT, class Src, class Tab>
+__device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
+                                              f32x4 (&Yim)[MT][CT], int strip0, int sstep) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -76,8 +178,6 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
       Tre[ct] = zero4();
       Tim[ct] = zero4();
     }
-    // stage 1 over column blocks, two register sets in ping-pong so the loads
-    // of one block are in flight while the other block's products issue
     auto stage1 = [&](const c4& a, const c4(&f)[CT]) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -111,7 +211,6 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
       stage1(a1, f1);
     }
     if (kb < NB) stage1(a0, f0);
-    // stage 2: Y[c1 tile][own tiles] += F[c1 tile, strip] * T[strip, own tiles]
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
       c4 fb = FA.f32((size_t)c1t * NB + strip, lane);
@@ -131,6 +230,18 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
       }
     }
   }
+}
+
+// Forward engine.  NB = ceil(n/16) row strips / column blocks.  FA holds
+// ctiles x NB blocks.  c2t0: first column tile this wave owns; the wave
+// runs strips strip0, strip0 + sstep, ...
+template <int MT, int CT, class Src, class Tab>
+__device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
+                                         f32x4 (&Yim)[MT][CT], int strip0 = 0, int sstep = 1) {
+  if constexpr (MT * CT <= 8)
+    fwd_wave_gauss<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
+  else
+    fwd_wave_four<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
 }
 
 // Forward engine for long windows whose twiddle table does not stay in the
@@ -229,10 +340,11 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
   }
 }
 
-// FP32 adjoint, stage 2 of column tile kt2 from the stage-1 accumulators S.
+// FP32 adjoint, stage 2 of column tile kt2 from the stage-1 accumulators S,
+// four products per complex product.
 template <int MT, int K1, class Sink, class Tab>
-__device__ __forceinline__ void adj_stage2_f32(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,
-                                               int kt2, Sink& sink) {
+__device__ __forceinline__ void adj_stage2_four(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,
+                                                int kt2, Sink& sink) {
   const int lane = lane_id();
   // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], K1 row tiles at a
   // time; the twiddle blocks of the next step are fetched while the current
@@ -282,6 +394,75 @@ __device__ __forceinline__ void adj_stage2_f32(const f32x4 (&Sre)[MT], const f32
     for (int u = 0; u < K1; ++u)
       if (k1t + u < NB) sink.template put<false>(k1t + u, kt2, Xre[u], Xim[u]);
   }
+}
+
+// FP32 adjoint, stage 2 of column tile kt2, three products per complex
+// product: conj(F) = c + id with c = Re F, d = -Im F, data S = a + ib, so
+//   k1 = a (Re F - Im F),  k2' = Im F (a + b),  k3 = Re F (b - a),
+//   Re X = k1 + k2',       Im X = k1 + k3
+// (k2' = -k2 of the Gauss form).  a + b and b - a are formed once per tile.
+template <int MT, int K1, class Sink, class Tab>
+__device__ __forceinline__ void adj_stage2_gauss(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB,
+                                                 const Tab& FT, int kt2, Sink& sink) {
+  const int lane = lane_id();
+  f32x4 Ssum[MT], Sdif[MT];
+#pragma unroll
+  for (int c = 0; c < MT; ++c) {
+    Ssum[c] = Sre[c] + Sim[c];
+    Sdif[c] = Sim[c] - Sre[c];
+  }
+  auto fetch2 = [&](int k1t, int c1t, c4(&f)[K1]) {
+#pragma unroll
+    for (int u = 0; u < K1; ++u) {
+      const int kt = (k1t + u < NB) ? k1t + u : NB - 1;
+      f[u] = FT.f32((size_t)kt * MT + c1t, lane);
+    }
+  };
+  c4 fb[2][K1];
+  fetch2(0, 0, fb[0]);
+  for (int k1t = 0; k1t < NB; k1t += K1) {
+    const int k1n = (k1t + K1 < NB) ? k1t + K1 : k1t;
+    f32x4 X1[K1], X2[K1], X3[K1];
+#pragma unroll
+    for (int u = 0; u < K1; ++u) {
+      X1[u] = zero4();
+      X2[u] = zero4();
+      X3[u] = zero4();
+    }
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      const int cur = c1t & 1;
+      if (c1t + 1 < MT)
+        fetch2(k1t, c1t + 1, fb[cur ^ 1]);
+      else if ((MT & 1) == 0)
+        fetch2(k1n, 0, fb[cur ^ 1]);  // cur ^ 1 == 0 here
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int u = 0; u < K1; ++u) {
+          const float fr = fb[cur][u].v[i].x, fi = fb[cur][u].v[i].y;
+          X1[u] = mfma4(fr - fi, Sre[c1t][i], X1[u]);
+          X2[u] = mfma4(fi, Ssum[c1t][i], X2[u]);
+          X3[u] = mfma4(fr, Sdif[c1t][i], X3[u]);
+        }
+      }
+    }
+    if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fb[0]);
+#pragma unroll
+    for (int u = 0; u < K1; ++u)
+      if (k1t + u < NB) sink.template put<false>(k1t + u, kt2, X1[u] + X2[u], X1[u] + X3[u]);
+  }
+}
+
+// FP32 adjoint, stage 2 of column tile kt2 from the stage-1 accumulators S.
+template <int MT, int K1, class Sink, class Tab>
+__device__ __forceinline__ void adj_stage2_f32(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,
+                                               int kt2, Sink& sink) {
+  if constexpr (MT <= 4 && K1 <= 2)
+    adj_stage2_gauss<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
+  else
+    adj_stage2_four<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
 }
 
 // Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
