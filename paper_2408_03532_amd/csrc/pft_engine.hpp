@@ -615,11 +615,18 @@ __device__ __forceinline__ void adj_patch_f32(const YSrc& ysrc, int NB, const Ta
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) y[kb][c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
   for (int kt2 = 0; kt2 < NB; ++kt2) {
-    f32x4 Sre[MT], Sim[MT];
+    // stage 1, S = Y conj(F), in three products: data y = a + ib, twiddle
+    // conj(F) = c + id (c = Re F, d = -Im F):
+    //   k1 = c (a + b),  k2' = a (Re F + Im F),  k3 = b (Re F - Im F),
+    //   Re S = k1 - k3,  Im S = k1 - k2'
+    // (k2' = -a (d - c) of the Gauss form); the two twiddle sums serve every
+    // row tile, a + b takes the place of the negation of the four-product form
+    f32x4 S1[MT], S2[MT], S3[MT];
 #pragma unroll
     for (int a = 0; a < MT; ++a) {
-      Sre[a] = zero4();
-      Sim[a] = zero4();
+      S1[a] = zero4();
+      S2[a] = zero4();
+      S3[a] = zero4();
     }
     c4 f[2];
     f[0] = FT.f32((size_t)kt2 * MT, lane);
@@ -630,19 +637,23 @@ __device__ __forceinline__ void adj_patch_f32(const YSrc& ysrc, int NB, const Ta
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const float fr = fc.v[s].x, fi = fc.v[s].y;
+        const float fsum = fr + fi, fdif = fr - fi;
 #pragma unroll
         for (int c1t = 0; c1t < MT; ++c1t) {
-          Sre[c1t] = mfma4(y[kb][c1t].v[s].x, fr, Sre[c1t]);
-          Sim[c1t] = mfma4(y[kb][c1t].v[s].y, fr, Sim[c1t]);
-        }
-#pragma unroll
-        for (int c1t = 0; c1t < MT; ++c1t) {
-          Sre[c1t] = mfma4(y[kb][c1t].v[s].y, fi, Sre[c1t]);
-          Sim[c1t] = mfma4(-y[kb][c1t].v[s].x, fi, Sim[c1t]);
+          const float ya = y[kb][c1t].v[s].x, yb = y[kb][c1t].v[s].y;
+          S1[c1t] = mfma4(ya + yb, fr, S1[c1t]);
+          S2[c1t] = mfma4(ya, fsum, S2[c1t]);
+          S3[c1t] = mfma4(yb, fdif, S3[c1t]);
         }
       }
     }
-    adj_stage2_f32<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      const f32x4 k1 = S1[a];
+      S1[a] = k1 - S3[a];
+      S2[a] = k1 - S2[a];
+    }
+    adj_stage2_f32<MT, K1>(S1, S2, NB, FT, kt2, sink);
   }
 }
 
