@@ -625,9 +625,6 @@ static int ew_blocks(size_t work) {
   return b < 1 ? 1 : (int)b;
 }
 
-// forward split: WR row groups so a chunk keeps the compute units busy, as
-// long as the partial spectra fit the LDS (WR - 1 copies of MT x MT tiles)
-
 // Workgroups of Kernel at `threads` threads (a multiple of 64, at most 1024)
 // that one compute unit holds at once; the first query of each kernel and
 // block size asks the runtime, later ones read the cache.
@@ -643,9 +640,13 @@ static int blocks_per_cu(int threads) {
   return n;
 }
 
+// forward split: WR row groups per position, summed through LDS (WR - 1
+// copies of the partial spectrum): two up to 64 kept coefficients (four
+// groups at m <= 32 spent more on the partial sums and the epilogue than the
+// extra waves gained), one above
 template <int MT>
 constexpr int pie_wr() {
-  return MT <= 2 ? 4 : (MT <= 4 ? 2 : 1);
+  return MT <= 4 ? 2 : 1;
 }
 
 template <class PR, int MT, bool TRACK>
@@ -653,7 +654,7 @@ static void fwd_launch(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   constexpr int CT = (MT <= 2) ? MT : 2;
   constexpr int WC = (MT + CT - 1) / CT;
   constexpr int WR = pie_wr<MT>();
-  static_assert(CT == (MT <= 2 ? MT : 2) && WR == (MT <= 2 ? 4 : (MT <= 4 ? 2 : 1)),
+  static_assert(CT == (MT <= 2 ? MT : 2) && WR == (MT <= 4 ? 2 : 1),
                 "the host-side split count assumes this work split");
   dim3 grid(cnt, a.splits), block(64 * WR * WC);
   const bool exact = a.n % 16 == 0;

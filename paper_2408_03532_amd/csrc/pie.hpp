@@ -68,7 +68,7 @@ constexpr int kStatBlocks = 2048;
 // CT column tiles per wave, WC column groups, WR row groups per workgroup.
 inline int pie_ct(int mt) { return mt <= 2 ? mt : 2; }
 inline int pie_wc(int mt) { return (mt + pie_ct(mt) - 1) / pie_ct(mt); }
-inline int pie_wr_rt(int mt) { return mt <= 2 ? 4 : (mt <= 4 ? 2 : 1); }
+inline int pie_wr_rt(int mt) { return mt <= 4 ? 2 : 1; }
 // Long windows split over several workgroups pass four strips at a time over
 // each twiddle block when every row group keeps at least eight strips.
 inline bool pie_fwd_rs(int nb, int wr, int splits) { return splits > 1 && nb >= 8 * wr * splits; }
