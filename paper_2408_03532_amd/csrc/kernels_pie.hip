@@ -41,28 +41,25 @@ __device__ __forceinline__ int pos_index(const int32_t* __restrict__ order, int 
 }
 
 // Gather source that also tracks max |P|^2 and max |O|^2 over what it reads.
+// (entries outside the patch are zeros and leave the maxima unchanged)
 template <bool EXACT>
 struct GatherTrackSrc {
+  using Raw = GatherRaw;
   GatherSrc<EXACT> g;
   mutable float mp, mo;
-  __device__ __forceinline__ c4 load(int row, int col0) const {
-    c4 v;
-    const float2* orow = g.O + (size_t)(g.r + row) * g.W + g.c + col0;
-    const float2* prow = g.P + (size_t)row * g.n + col0;
+  __device__ __forceinline__ Raw load_raw(int row, int col0) const { return g.load_raw(row, col0); }
+  __device__ __forceinline__ c4 combine(const Raw& v) const {
+    c4 z;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int col = col0 + s;
-      if (EXACT || (row < g.n && col < g.n)) {
-        const float2 p = prow[s], o = orow[s];
-        mp = fmaxf(mp, p.x * p.x + p.y * p.y);
-        mo = fmaxf(mo, o.x * o.x + o.y * o.y);
-        v.v[s] = cmul(p, o);
-      } else {
-        v.v[s] = make_float2(0.f, 0.f);
-      }
+      const float2 p = v.p.v[s], o = v.o.v[s];
+      mp = fmaxf(mp, p.x * p.x + p.y * p.y);
+      mo = fmaxf(mo, o.x * o.x + o.y * o.y);
+      z.v[s] = cmul(p, o);
     }
-    return v;
+    return z;
   }
+  __device__ __forceinline__ c4 load(int row, int col0) const { return combine(load_raw(row, col0)); }
 };
 
 // Magnitude projection (eq. (3)) of coefficient (c1, c2) of chunk entry q:

@@ -23,9 +23,43 @@
 // zero outside the m x n matrix.  Each block is 2 KB (see load_tw).
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace pftpie {
+
+// Operand sources may split a load into its memory part (load_raw, whose
+// result sits in the prefetch registers) and the arithmetic on it (combine,
+// applied just before the block's products), so that a prefetched block is
+// not waited for when it is fetched.  Sources without that split (plain
+// patches, coefficients) load in full.
+template <class S, class = void>
+struct RawOf {
+  using type = c4;
+  static constexpr bool split = false;
+};
+template <class S>
+struct RawOf<S, std::void_t<typename S::Raw>> {
+  using type = typename S::Raw;
+  static constexpr bool split = true;
+};
+
+template <class S>
+__device__ __forceinline__ typename RawOf<S>::type load_raw(const S& src, int row, int col0) {
+  if constexpr (RawOf<S>::split)
+    return src.load_raw(row, col0);
+  else
+    return src.load(row, col0);
+}
+
+template <class S>
+__device__ __forceinline__ c4 combine(const S& src, const typename RawOf<S>::type& r) {
+  if constexpr (RawOf<S>::split)
+    return src.combine(r);
+  else
+    return r;
+}
 
 // psi source of the plain transform: patch p, side n.  EXACT: n % 16 == 0
 // and 16-byte aligned base, so every lane chunk is in bounds and aligned.
@@ -90,7 +124,9 @@ __device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab
     // stage 1 over column blocks (data psi, twiddle F^T), two register sets
     // in ping-pong so the loads of one block are in flight while the other
     // block's products issue
-    auto stage1 = [&](const c4& a, const c4(&f)[CT]) {
+    using Raw = typename RawOf<Src>::type;
+    auto stage1 = [&](const Raw& raw, const c4(&f)[CT]) {
+      const c4 a = combine(src, raw);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const float ar = a.v[s].x, ai = a.v[s].y;
@@ -104,12 +140,13 @@ __device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab
         }
       }
     };
-    auto fetch = [&](int kb, c4& a, c4(&f)[CT]) {
-      a = src.load(row, kb * 16 + 4 * g);
+    auto fetch = [&](int kb, Raw& a, c4(&f)[CT]) {
+      a = load_raw(src, row, kb * 16 + 4 * g);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) f[ct] = FA.f32((size_t)(c2t0 + ct) * NB + kb, lane);
     };
-    c4 a0, a1, f0[CT], f1[CT];
+    Raw a0, a1;
+    c4 f0[CT], f1[CT];
     fetch(0, a0, f0);
     int kb = 0;
     for (; kb + 1 < NB; kb += 2) {
@@ -178,7 +215,9 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
       Tre[ct] = zero4();
       Tim[ct] = zero4();
     }
-    auto stage1 = [&](const c4& a, const c4(&f)[CT]) {
+    using Raw = typename RawOf<Src>::type;
+    auto stage1 = [&](const Raw& raw, const c4(&f)[CT]) {
+      const c4 a = combine(src, raw);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const float ar = a.v[s].x, ai = a.v[s].y, nai = -ai;
@@ -194,12 +233,13 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
         }
       }
     };
-    auto fetch = [&](int kb, c4& a, c4(&f)[CT]) {
-      a = src.load(row, kb * 16 + 4 * g);
+    auto fetch = [&](int kb, Raw& a, c4(&f)[CT]) {
+      a = load_raw(src, row, kb * 16 + 4 * g);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) f[ct] = FA.f32((size_t)(c2t0 + ct) * NB + kb, lane);
     };
-    c4 a0, a1, f0[CT], f1[CT];
+    Raw a0, a1;
+    c4 f0[CT], f1[CT];
     fetch(0, a0, f0);
     int kb = 0;
     for (; kb + 1 < NB; kb += 2) {
@@ -277,7 +317,11 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
         Tre[r][ct] = zero4();
         Tim[r][ct] = zero4();
       }
-    auto stage1 = [&](const c4(&a)[RS], const c4(&f)[CT]) {
+    using Raw = typename RawOf<Src>::type;
+    auto stage1 = [&](const Raw(&raw)[RS], const c4(&f)[CT]) {
+      c4 a[RS];
+#pragma unroll
+      for (int r = 0; r < RS; ++r) a[r] = combine(src, raw[r]);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -295,13 +339,14 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
           }
         }
     };
-    auto fetch = [&](int kb, c4(&a)[RS], c4(&f)[CT]) {
+    auto fetch = [&](int kb, Raw(&a)[RS], c4(&f)[CT]) {
 #pragma unroll
-      for (int r = 0; r < RS; ++r) a[r] = src.load(rows[r], kb * 16 + 4 * g);
+      for (int r = 0; r < RS; ++r) a[r] = load_raw(src, rows[r], kb * 16 + 4 * g);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) f[ct] = FA.f32((size_t)(c2t0 + ct) * NB + kb, lane);
     };
-    c4 a0[RS], a1[RS], f0[CT], f1[CT];
+    Raw a0[RS], a1[RS];
+    c4 f0[CT], f1[CT];
     fetch(0, a0, f0);
     int kb = 0;
     for (; kb + 1 < NB; kb += 2) {

@@ -135,26 +135,41 @@ int pie_probe_blocks(int n);
 
 #ifdef __HIPCC__
 // psi[k1][k2] = P[k1][k2] * O[r + k1][c + k2]; zero outside the n x n patch.
+// The engines prefetch the raw probe and object values (load_raw) and form
+// the products (combine) just before the block's MFMA products.
+struct GatherRaw {
+  c4 p, o;
+};
+
 template <bool EXACT>
 struct GatherSrc {
+  using Raw = GatherRaw;
   const float2* __restrict__ O;
   const float2* __restrict__ P;
   int W, n, r, c;
-  __device__ __forceinline__ c4 load(int row, int col0) const {
-    c4 v;
+  __device__ __forceinline__ Raw load_raw(int row, int col0) const {
+    Raw v;
     const float2* orow = O + (size_t)(r + row) * W + c + col0;
     const float2* prow = P + (size_t)row * n + col0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int col = col0 + s;
       if (EXACT || (row < n && col < n)) {
-        v.v[s] = cmul(prow[s], orow[s]);
+        v.p.v[s] = prow[s];
+        v.o.v[s] = orow[s];
       } else {
-        v.v[s] = make_float2(0.f, 0.f);
+        v.p.v[s] = v.o.v[s] = make_float2(0.f, 0.f);
       }
     }
     return v;
   }
+  __device__ __forceinline__ c4 combine(const Raw& v) const {
+    c4 z;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) z.v[s] = cmul(v.p.v[s], v.o.v[s]);
+    return z;
+  }
+  __device__ __forceinline__ c4 load(int row, int col0) const { return combine(load_raw(row, col0)); }
 };
 
 #endif
