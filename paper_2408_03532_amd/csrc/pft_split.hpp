@@ -120,8 +120,11 @@ template <class PR, int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab& FA, int c2t0,
                                                f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
                                                int sstep = 1, int rot = 0) {
-  static_assert(kSplitRing % 2 == 0, "ring size must be even");
-  constexpr int RING = kSplitRing;
+  static_assert(kSplitRing % 4 == 0, "ring size must be a multiple of 4");
+  // raw exit-wave operands (probe and object values, twice the registers of
+  // a formed block) take half the ring depth
+  using Raw = typename RawOf<Src>::type;
+  constexpr int RING = RawOf<Src>::split ? kSplitRing / 2 : kSplitRing;
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -175,7 +178,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
       Tim[ct] = zero4();
     }
   };
-  c4 a[RING];
+  Raw a[RING];
   TwS<PR> f[2][CT];
   SplitOp<PR> op[2];
   // one chunk step of a ring turn starting at chunk q0 (q0 % RING == 0 within
@@ -185,7 +188,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
     a[(u + RING - 1) % RING] = load_a(q0 + u + RING - 1);
     load_f(q0 + u + 1, f[(u + 1) & 1]);
     __builtin_amdgcn_sched_barrier(0);
-    op[(u + 1) & 1] = split_c4<PR, false>(a[(u + 1) % RING]);
+    op[(u + 1) & 1] = split_c4<PR, false>(combine(src, a[(u + 1) % RING]));
     products(op[u & 1], f[u & 1]);
   };
   auto start = [&](auto load_a, auto load_f) {
@@ -197,7 +200,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
 #pragma unroll
     for (int u = 0; u < RING - 1; ++u) a[u] = load_a(u);
     load_f(0, f[0]);
-    op[0] = split_c4<PR, false>(a[0]);
+    op[0] = split_c4<PR, false>(combine(src, a[0]));
   };
   if (NB % RING == 0) {
     // one sequence over all the wave's strips; whole ring turns carry no
@@ -211,7 +214,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
       const int j = q / NB;
       int k = q - j * NB + rot;
       k = k < NB ? k : k - NB;
-      return src.load((strip0 + j * sstep) * 16 + r16, k * 16 + 4 * g);
+      return load_raw(src, (strip0 + j * sstep) * 16 + r16, k * 16 + 4 * g);
     };
     auto load_f = [&](int q, TwS<PR>(&fr)[CT]) {
       int k = (q < nq ? q : nq - 1) % NB + rot;
@@ -230,7 +233,7 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
   } else {
     for (int strip = strip0; strip < NB; strip += sstep) {
       const int row = strip * 16 + r16;
-      auto load_a = [&](int kb) { return src.load(row, (kb < NB ? kb : NB - 1) * 16 + 4 * g); };
+      auto load_a = [&](int kb) { return load_raw(src, row, (kb < NB ? kb : NB - 1) * 16 + 4 * g); };
       auto load_f = [&](int kb, TwS<PR>(&fr)[CT]) {
         const int k = kb < NB ? kb : NB - 1;
 #pragma unroll
