@@ -233,7 +233,7 @@ def pie_tiny_rate(torch, pk, batch, norm, sweeps=10, warmup=2):
     import workloads
     case = workloads.tiny_pie()
     scan = pk.Scan(case["pos"], (128, 128), 32, 16)
-    amp = torch.from_numpy(case["amp"]).cuda()
+    amp = pk.crop_amplitudes(torch.from_numpy(case["intensity"]).cuda(), 16)
     O = torch.from_numpy(case["init"]).cuda()
     P = torch.from_numpy(case["probe"]).cuda()
     prm = pk.PieParams(batch=batch, norm=norm, beta=1.0, alpha=1e-3)

@@ -100,7 +100,7 @@ pftpie_status pftpie_plan_create_method(int32_t n, int32_t m, pftpie_precision p
                                         pftpie_method method, pftpie_plan* out);
 /* The method a plan resolved to (DENSE or FFT). */
 pftpie_status pftpie_plan_method(pftpie_plan plan, pftpie_method* method);
-/* Masked larger field (Sec. 4.2: an n x n illuminated window inside a
+/* Masked larger field (Sec. 4.1.3: an n x n illuminated window inside a
  * period x period field, every other pixel zero): the plan's transform uses
  * DFT length `period` (n <= period <= 2^20),
  *   F_m[c][k] = exp(-2 pi i ((t_c k) mod period) / period),  k < n,
@@ -121,9 +121,11 @@ pftpie_status pftpie_plan_destroy(pftpie_plan plan);
 pftpie_status pftpie_plan_info(pftpie_plan plan, int32_t* n, int32_t* m,
                                pftpie_precision* prec);
 
-/* Autotuner: times the plan's candidate tile splits (forward column tiles
- * per wave, LDS-resident or L2-resident twiddle tables for both directions)
- * on a zero-filled scratch batch of `sample` patches and keeps the fastest.
+/* Autotuner: times the plan's candidate launch choices on a scratch batch of
+ * `sample` patches filled with random values (uniform in [-1, 1)) and keeps
+ * the fastest: forward column tiles per wave and an LDS-resident or
+ * L2-resident twiddle table; adjoint LDS or L2 table, a whole patch or one
+ * column tile per wave, and (FP32) row tiles per step and workgroup size.
  * Allocates and frees scratch memory and synchronises the device; call it
  * before the plan is used from other threads or streams (it changes the
  * plan's launch choices, never its results' definition).  best_ms (may be
@@ -235,7 +237,11 @@ typedef struct {
 pftpie_status pie_workspace_size(pie_scan scan, const pie_params* p, size_t* bytes);
 
 /* One sweep over all J positions, in chunks of p->batch of the order
- * order_dev (device int32 permutation of [0, J), or NULL for scan order).
+ * order_dev (device int32 [J]: a permutation of [0, J), or NULL for scan
+ * order).  An entry outside [0, J) names no position: it keeps its place in
+ * its chunk and contributes nothing.  A position listed more than once is
+ * not supported (the result is then unspecified; the device holds the
+ * order, so the host cannot check it).
  * For each position j of a chunk, against the object and probe as they
  * were at the chunk start:
  *   psi = P * O[window j];  u = F_m psi F_m^T;

@@ -39,7 +39,7 @@ def twiddles(n, m, period=None):
 
     The DFT kernel of Sec. 3.1.1, eq. (7), restricted to the kept rows t_c.
     A period N > n is the masked full field of the paper's experiments
-    (Sec. 4.2: an n x n illuminated window inside an N x N field, every
+    (Sec. 4.1.3: an n x n illuminated window inside an N x N field, every
     other pixel zero): the field's DFT at frequency t only sums the window's
     pixels, k = 0..n-1 counted from the window's corner.  The phase t_c*k is
     reduced modulo N in integer arithmetic before the trigonometric call, so

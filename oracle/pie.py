@@ -67,7 +67,9 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
 
     obj   [H][W] complex, probe [n][n] complex, pos [J][2] integer top-left
     (row, col) offsets, amp [J][m][m] real cropped amplitudes, order a
-    permutation of range(J) or None for scan order.
+    permutation of range(J) or None for scan order.  An order entry outside
+    range(J) names no position: it takes its place in its chunk and
+    contributes nothing (the chunks stay those of the order as given).
 
     Returns (obj_new, probe_new, stats) with stats =
     (phi, ||dO||^2, ||O||^2, n_nonfinite):
@@ -76,7 +78,7 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
       dO    = object after minus object before the sweep;
       n_nonfinite counts non-finite entries of the new object (and probe).
 
-    period: the masked-field form of the experiments (Sec. 4.2): the object
+    period: the masked-field form of the experiments (Sec. 4.1.3): the object
     is the whole N x N field (N = period), exit wave j is the field masked
     to the n x n window at pos[j] (times the probe), its data are the kept
     coefficients of the field's N-point DFT (``pft.forward`` with period N
@@ -116,6 +118,8 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
         numP = np.zeros_like(P)
         E = np.zeros(P.shape, dtype=np.float64)
         for j in chunk:
+            if not 0 <= j < J:
+                continue
             r, c = pos[j]
             Oj = O[r:r + n, c:c + n]
             psi = P * Oj                                   # exit wave, eq. (1)
@@ -134,6 +138,8 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
             if literal:
                 # eq. (6) at the updated object: new exit wave, new projection
                 (j,) = chunk
+                if not 0 <= j < J:
+                    continue
                 r, c = pos[j]
                 Oj = O[r:r + n, c:c + n]
                 shift = None if period is None else (r, c)
@@ -143,8 +149,11 @@ def pie_sweep(obj, probe, pos, amp, m, order=None, batch=1, norm=0,
             elif gamma > 0.0:
                 P = P + gamma * numP
         else:
-            O = O + beta * numO / (D + alpha * D.max())
-            if gamma > 0.0:
+            # unlit pixels (D = 0) have numO = 0 and stay as they are; a chunk
+            # that lights nothing changes nothing
+            if D.max() > 0.0:
+                O = O + beta * numO / (D + alpha * D.max())
+            if gamma > 0.0 and E.max() > 0.0:
                 P = P + gamma * numP / (E + alpha * E.max())
     phi = phi_acc / (J * N * N)
     dO2 = float(np.sum(np.abs(O - O_start) ** 2))

@@ -420,8 +420,8 @@ __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, in
       cv[u] = make_int2(0, 0);
       if (eb + u < e1) {
         const int j = a.tile_pos[eb + u];
-        const int q = a.rank[j] - c0;
-        if (q >= 0 && q < cnt) qv[u] = q;
+        const int rk = a.rank[j];
+        if (rk >= c0 && rk - c0 < cnt) qv[u] = rk - c0;
         cv[u] = a.pos[j];
       }
     }
@@ -521,23 +521,32 @@ __global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
   }
 }
 
-// Sweep start: O0 = O, ranks of the sweep order, cleared per-position slots.
+// Sweep start: O0 = O, cleared per-position slots, and the ranks: the scan
+// order's own (no order), else every rank cleared to "absent" for
+// k_pie_rank to fill, so that a position the order leaves out is never
+// gathered from a stale workspace slot.
 __global__ __launch_bounds__(256) void k_pie_begin(PieArgs a) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t total = (size_t)a.H * a.W;
   for (size_t t = t0; t < total; t += stride) a.O0[t] = a.O[t];
   for (size_t t = t0; t < (size_t)a.J; t += stride) {
-    if (a.order) {
-      const int j = a.order[t];
-      if (j >= 0 && j < a.J) a.rank[j] = (int)t;
-    } else {
-      a.rank[t] = (int)t;
-    }
+    a.rank[t] = a.order ? kRankAbsent : (int)t;
     a.winmax[2 * t] = 0u;
     a.winmax[2 * t + 1] = 0u;
   }
   for (size_t t = t0; t < (size_t)a.J * 4; t += stride) a.phi_part[t] = 0.0;
+}
+
+// rank[order[t]] = t for the entries of the order inside [0, J); a position
+// listed twice keeps its first place (the least t), whatever the order in
+// which the threads run.
+__global__ __launch_bounds__(256) void k_pie_rank(PieArgs a) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < (size_t)a.J; t += stride) {
+    const int j = a.order[t];
+    if (j >= 0 && j < a.J) atomicMin(&a.rank[j], (int)t);
+  }
 }
 
 // Statistics partials per block: ||O - O0||^2, ||O0||^2, non-finite count.
@@ -767,6 +776,7 @@ hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipS
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   const size_t obj = (size_t)a.H * a.W;
   hipLaunchKernelGGL(k_pie_begin, dim3(ew_blocks(obj)), dim3(256), 0, st, a);
+  if (a.order) hipLaunchKernelGGL(k_pie_rank, dim3(ew_blocks((size_t)a.J)), dim3(256), 0, st, a);
   const int ntiles = a.tiles_x * a.tiles_y;
   const int pblocks = pie_probe_blocks(a.n);
   auto run_chunk = [&](const PieArgs& ca, int c0, int cnt) -> hipError_t {

@@ -63,6 +63,7 @@ struct PieArgs {
 };
 
 constexpr int kStatBlocks = 2048;
+constexpr int32_t kRankAbsent = 0x7fffffff;  // rank of a position the sweep order leaves out
 
 // Forward work split of the dense sweep for MT = ceil(m/16) tiles per axis:
 // CT column tiles per wave, WC column groups, WR row groups per workgroup.

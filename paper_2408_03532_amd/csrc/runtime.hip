@@ -49,6 +49,31 @@ static pftpie_status check_batch_io(const pftpie_plan_s* p, const void* in, size
   return PFTPIE_OK;
 }
 
+// Fills x[i] with float pairs uniform in [-1, 1) from a counter-based hash
+// of i (timing operands only: zeros would run the matrix cores at a higher
+// clock than real data do).
+__global__ __launch_bounds__(256) void k_tune_fill(float2* __restrict__ x, size_t count, uint32_t salt) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32) ^ salt;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    const float a = (float)(h & 0xFFFFu) * (1.f / 32768.f) - 1.f;
+    const float b = (float)(h >> 16) * (1.f / 32768.f) - 1.f;
+    x[i] = make_float2(a, b);
+  }
+}
+
+static hipError_t tune_fill(float2* x, size_t count, uint32_t salt, hipStream_t st) {
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)blocks), dim3(256), 0, st, x, count, salt);
+  return hipGetLastError();
+}
+
 }  // namespace pftpie
 
 using namespace pftpie;
@@ -107,19 +132,12 @@ pftpie_status pftpie_plan_create_period(int32_t n, int32_t m, int32_t period, pf
   p->method = use_fft ? PFTPIE_METHOD_FFT : PFTPIE_METHOD_DENSE;
   p->fft_tw = nullptr;
   p->fwd_ct = prec == PFTPIE_FP32 ? fwd_ct_default(p->mt) : fwd_ct_default_split(p->mt);
+  // launch choices; pftpie_plan_autotune may replace them by measured ones
   p->use_lds = 1;
   p->use_lds_adj = 1;
   p->adj_k1 = 2;
-  if (const char* env = std::getenv("PFTPIE_ADJ_K1")) p->adj_k1 = std::atoi(env) == 4 ? 4 : 2;
   p->adj_patch = 1;
-  if (const char* env = std::getenv("PFTPIE_ADJ_PATCH")) p->adj_patch = std::atoi(env) != 0;
   p->adj_threads = 512;
-  if (const char* env = std::getenv("PFTPIE_ADJ_THREADS")) p->adj_threads = std::atoi(env) == 768 ? 768 : 512;
-  if (const char* env = std::getenv("PFTPIE_LDS")) p->use_lds = p->use_lds_adj = std::atoi(env) != 0;
-  if (const char* env = std::getenv("PFTPIE_FWD_CT")) {  // tuning override
-    const int ct = std::atoi(env);
-    if (fwd_ct_valid(p->mt, ct)) p->fwd_ct = ct;
-  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
@@ -242,18 +260,23 @@ pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* bes
   const std::string key = std::string(prop.gcnArchName) + " " + std::to_string(plan->n) + " " +
                           std::to_string(plan->m) + " " + std::to_string((int)plan->prec);
   const char* cache = std::getenv("PFTPIE_TUNE_CACHE");
-  if (cache) {  // "<arch> <n> <m> <prec> <fwd_ct> <lds_fwd> <lds_adj> <ms>" per line
+  if (cache) {
+    // "<arch> <n> <m> <prec> <fwd_ct> <lds_fwd> <lds_adj> <adj_patch> <adj_k1> <adj_threads> <ms>" per line
     if (FILE* f = std::fopen(cache, "r")) {
       char arch[128];
-      int n, m, pr, ct, lf, la;
+      int n, m, pr, ct, lf, la, ap, k1, th;
       double ms;
-      while (std::fscanf(f, "%127s %d %d %d %d %d %d %lf", arch, &n, &m, &pr, &ct, &lf, &la, &ms) == 8) {
+      while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %d %d %lf", arch, &n, &m, &pr, &ct, &lf, &la, &ap, &k1, &th,
+                         &ms) == 11) {
         const std::string k2 = std::string(arch) + " " + std::to_string(n) + " " + std::to_string(m) + " " +
                                std::to_string(pr);
-        if (k2 == key && fwd_ct_valid(plan->mt, ct)) {
+        if (k2 == key && fwd_ct_valid(plan->mt, ct) && (k1 == 2 || k1 == 4) && (th == 512 || th == 768)) {
           plan->fwd_ct = ct;
-          plan->use_lds = lf;
-          plan->use_lds_adj = la;
+          plan->use_lds = lf != 0;
+          plan->use_lds_adj = la != 0;
+          plan->adj_patch = ap != 0;
+          plan->adj_k1 = k1;
+          plan->adj_threads = th;
           if (best_ms) *best_ms = ms;
           std::fclose(f);
           return PFTPIE_OK;
@@ -268,9 +291,9 @@ pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* bes
   hipEvent_t e0 = nullptr, e1 = nullptr;
   e = hipMalloc((void**)&x, nin * 8);
   if (e == hipSuccess) e = hipMalloc((void**)&y, nout * 8);
-  if (e == hipSuccess) e = hipMemset(x, 0, nin * 8);
-  if (e == hipSuccess) e = hipMemset(y, 0, nout * 8);
   if (e == hipSuccess) e = hipStreamCreate(&st);
+  if (e == hipSuccess) e = tune_fill(x, nin, 0x1234567u, st);
+  if (e == hipSuccess) e = tune_fill(y, nout, 0x89abcdefu, st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   auto cleanup = [&]() {
@@ -284,6 +307,8 @@ pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* bes
     cleanup();
     return fail(PFTPIE_E_NOMEM, std::string("plan_autotune: scratch: ") + hipGetErrorString(e));
   }
+  // each candidate runs on random operands: the adjoint writes x, so the
+  // forward candidates, which read x, are all timed first
   auto time_ms = [&](bool fwd) -> double {
     double best = 1e30;
     for (int rep = 0; rep < 4; ++rep) {
@@ -298,7 +323,7 @@ pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* bes
     return best;
   };
   double best_f = 1e30, best_a = 1e30;
-  int best_ct = plan->fwd_ct, best_lf = plan->use_lds, best_la = plan->use_lds_adj;
+  int best_ct = plan->fwd_ct, best_lf = plan->use_lds;
   for (int ct = 1; ct <= 4; ++ct) {
     if (!fwd_ct_valid(plan->mt, ct)) continue;
     for (int lf = 1; lf >= 0; --lf) {
@@ -312,24 +337,48 @@ pftpie_status pftpie_plan_autotune(pftpie_plan plan, int64_t sample, double* bes
       }
     }
   }
-  for (int la = 1; la >= 0; --la) {
-    plan->use_lds_adj = la;
-    const double t = time_ms(false);
-    if (t < best_a) {
-      best_a = t;
-      best_la = la;
-    }
-  }
   plan->fwd_ct = best_ct;
   plan->use_lds = best_lf;
+  // the forward's output y is the adjoint's input: refill it with random data
+  if (tune_fill(y, nout, 0x89abcdefu, st) != hipSuccess) {
+    cleanup();
+    return fail(PFTPIE_E_DEVICE, "plan_autotune: fill");
+  }
+  // adjoint: LDS or L2 table, whole patch per wave or tile per wave, and for
+  // FP32 the stage-2 row tiles per step and the workgroup size
+  const bool f32 = plan->prec == PFTPIE_FP32;
+  int best_la = plan->use_lds_adj, best_ap = plan->adj_patch, best_k1 = plan->adj_k1, best_th = plan->adj_threads;
+  for (int la = 1; la >= 0; --la)
+    for (int ap = 1; ap >= 0; --ap)
+      for (int k1 = 2; k1 <= (f32 ? 4 : 2); k1 += 2)
+        for (int th = 512; th <= (f32 ? 768 : 512); th += 256) {
+          // duplicates: the whole-patch kernels (m <= 64) take neither k1
+          // nor the workgroup size, and above m = 64 there is no whole-patch kernel
+          if (ap && (plan->mt > 4 || k1 != 2 || th != 512)) continue;
+          plan->use_lds_adj = la;
+          plan->adj_patch = ap;
+          plan->adj_k1 = k1;
+          plan->adj_threads = th;
+          const double t = time_ms(false);
+          if (t < best_a) {
+            best_a = t;
+            best_la = la;
+            best_ap = ap;
+            best_k1 = k1;
+            best_th = th;
+          }
+        }
   plan->use_lds_adj = best_la;
+  plan->adj_patch = best_ap;
+  plan->adj_k1 = best_k1;
+  plan->adj_threads = best_th;
   cleanup();
   if (best_f >= 1e30 || best_a >= 1e30) return fail(PFTPIE_E_DEVICE, "plan_autotune: every candidate failed");
   if (best_ms) *best_ms = best_f + best_a;
   if (cache) {
     if (FILE* f = std::fopen(cache, "a")) {
-      std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", prop.gcnArchName, plan->n, plan->m, (int)plan->prec, best_ct,
-                   best_lf, best_la, best_f + best_a);
+      std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %.6f\n", prop.gcnArchName, plan->n, plan->m, (int)plan->prec,
+                   best_ct, best_lf, best_la, best_ap, best_k1, best_th, best_f + best_a);
       std::fclose(f);
     }
   }

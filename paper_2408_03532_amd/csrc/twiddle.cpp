@@ -1,6 +1,6 @@
 // Partial DFT matrix F_m[c][k] = exp(-2 pi i t_c k / N), t_c = c - floor(m/2),
 // k < n (the DFT kernel of Sec. 3.1.1 restricted to the kept window; N = n,
-// or the DFT length of a masked larger field, Sec. 4.2), built in double and
+// or the DFT length of a masked larger field, Sec. 4.1.3), built in double and
 // laid out in the kernels' tile order.  The phase t_c * k is reduced modulo
 // N in 64-bit integers before the trigonometric call so the angle stays in
 // [0, 2 pi) whatever the sizes.

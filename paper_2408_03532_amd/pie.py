@@ -148,7 +148,7 @@ def hybrid_pie(obj, probe, pos, intensity, m, iters_pft=50, tol_pft=1e-2, iters_
     (full_method "auto"; "dense" forces the contraction at m = n).
     order: None (scan order), a device int32 permutation, or "random" for
     a fresh permutation of the positions in every sweep (uniformly at
-    random without replacement, Sec. 4.3; numpy generator seeded with
+    random without replacement, Sec. 4.2.1; numpy generator seeded with
     order_seed).
     Returns the history [(phase, sweep, Phi, rel_change)].  The only host
     synchronisation is the read-back of the 4 statistics per sweep.

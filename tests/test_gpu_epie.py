@@ -2,7 +2,7 @@
 at the updated object, with the exit wave and projection formed again)
 against the FP64 oracle, for the dense contraction (m < n) and the
 full-window fast transform (m = n), in random orders without replacement,
-and on the blind circular-window geometry of Sec. 4.3.
+and on the blind circular-window geometry of Sec. 4.2.
 
 Tolerances: relative L2 <= 1e-5 for object and probe after one sweep from a
 common state (FP32), Phi <= 1e-5 relative.
@@ -39,13 +39,19 @@ def blind():
     return workloads.blind_circular()
 
 
+def amps(pk, intensity, m):
+    """Each side crops the data itself (Algorithm 3): the library's crop
+    kernel on the device, the oracle's crop in float64 on the host."""
+    return pk.crop_amplitudes(torch.from_numpy(intensity).cuda(), m), opie.amplitudes(intensity, m)
+
+
 def run(pk, case, init, probe0, amp, m, prm, order):
     n = probe0.shape[0]
     scan = pk.Scan(case["pos"], init.shape, n, m)
     O = torch.from_numpy(init.astype(np.complex64)).cuda()
     P = torch.from_numpy(probe0.astype(np.complex64)).cuda()
     ordt = torch.from_numpy(np.asarray(order, dtype=np.int32)).cuda()
-    st = pk.pie_sweep(O, P, scan, torch.from_numpy(amp.astype(np.float32)).cuda(), prm, order=ordt)
+    st = pk.pie_sweep(O, P, scan, amp, prm, order=ordt)
     return O.cpu().numpy(), P.cpu().numpy(), st.cpu().numpy(), scan.plan.method
 
 
@@ -54,11 +60,11 @@ def run(pk, case, init, probe0, amp, m, prm, order):
 def test_literal_probe_step_matches_oracle(pk, tiny, m, beta, gamma):
     print("literal epie", m, beta, gamma, flush=True)
     n = tiny["probe"].shape[0]
-    amp = workloads.crop_amplitudes(tiny["intensity"], m)
+    A, amp = amps(pk, tiny["intensity"], m)
     P0 = tiny["probe"] * (1.0 + 0.05j)
     order = np.random.default_rng(11).permutation(len(tiny["pos"]))
     prm = dict(batch=1, norm=0, beta=beta, gamma=gamma)
-    O, P, st, method = run(pk, tiny, tiny["init"], P0, amp, m,
+    O, P, st, method = run(pk, tiny, tiny["init"], P0, A, m,
                            pk.PieParams(probe_update="literal", **prm), order)
     assert method == ("fft" if m == n else "dense")
     Or, Pr, sr = opie.pie_sweep(tiny["init"], P0, tiny["pos"], amp, m, order=order,
@@ -76,7 +82,7 @@ def test_literal_probe_step_needs_sequential_plain_steps(pk, tiny):
     scan = pk.Scan(tiny["pos"], tiny["init"].shape, n, 16)
     O = torch.from_numpy(tiny["init"]).cuda()
     P = torch.from_numpy(tiny["probe"]).cuda()
-    A = torch.from_numpy(tiny["amp"]).cuda()
+    A, _ = amps(pk, tiny["intensity"], 16)
     for bad in (dict(batch=4), dict(norm=1)):
         prm = pk.PieParams(gamma=0.5, probe_update="literal", **bad)
         with pytest.raises(pk.PftpieError):
@@ -89,10 +95,10 @@ def test_blind_circular_sweep_matches_oracle(pk, blind, m):
     # windows, 16 positions, random order) from the initial object and the
     # smaller initial circle, partial (m = 32) and full window (m = 128)
     print("blind circular sweep", m, flush=True)
-    amp = workloads.crop_amplitudes(blind["intensity"], m)
+    A, amp = amps(pk, blind["intensity"], m)
     order = np.random.default_rng(12).permutation(len(blind["pos"]))
     prm = dict(batch=1, norm=0, beta=1.0, gamma=0.5)
-    O, P, st, _ = run(pk, blind, blind["init"], blind["probe_init"], amp, m,
+    O, P, st, _ = run(pk, blind, blind["init"], blind["probe_init"], A, m,
                       pk.PieParams(probe_update="literal", **prm), order)
     Or, Pr, sr = opie.pie_sweep(blind["init"], blind["probe_init"], blind["pos"], amp, m, order=order,
                                 probe_update="literal", **prm)

@@ -27,6 +27,12 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def amps(pk, intensity, m):
+    """Each side crops the data itself (Algorithm 3): the library's crop
+    kernel on the device, the oracle's crop in float64 on the host."""
+    return pk.crop_amplitudes(torch.from_numpy(intensity).cuda(), m), opie.amplitudes(intensity, m)
+
+
 @pytest.fixture(scope="module")
 def pk():
     import paper_2408_03532_amd as p
@@ -105,14 +111,13 @@ MODES = [dict(batch=1, norm=0, beta=1.0, gamma=0.0),
 def test_pie_sweep_full_window_matches_oracle(pk, tiny, mode):
     print("fft pie sweep", mode, flush=True)
     n = tiny["probe"].shape[0]
-    amp = workloads.crop_amplitudes(tiny["intensity"], n)
+    A, amp = amps(pk, tiny["intensity"], n)
     init = tiny["init"]
     P0 = tiny["probe"] * (1.0 + 0.05j) if mode.get("gamma", 0) else tiny["probe"]
     scan = pk.Scan(tiny["pos"], init.shape, n, n, method="fft")
     assert scan.plan.method == "fft"
     O = torch.from_numpy(init.astype(np.complex64)).cuda()
     P = torch.from_numpy(P0.astype(np.complex64)).cuda()
-    A = torch.from_numpy(amp.astype(np.float32)).cuda()
     st = pk.pie_sweep(O, P, scan, A, pk.PieParams(**mode)).cpu().numpy()
     Or, Pr, sr = opie.pie_sweep(init, P0, tiny["pos"], amp, n, **mode)
     assert rel(O.cpu().numpy(), Or) <= 1e-5
@@ -127,7 +132,7 @@ def test_pie_sweep_order_and_invalid_entries(pk, tiny):
     # nothing, the rest follow the permutation
     print("fft pie order", flush=True)
     n = tiny["probe"].shape[0]
-    amp = workloads.crop_amplitudes(tiny["intensity"], n)
+    A0, amp = amps(pk, tiny["intensity"], n)
     J = len(tiny["pos"])
     order = np.random.default_rng(7).permutation(J).astype(np.int32)
     order_bad = order.copy()
@@ -136,7 +141,7 @@ def test_pie_sweep_order_and_invalid_entries(pk, tiny):
     for ordr in (order, order_bad):
         O = torch.from_numpy(tiny["init"]).cuda()
         P = torch.from_numpy(tiny["probe"]).cuda()
-        A = torch.from_numpy(amp).cuda()
+        A = A0
         prm = pk.PieParams(batch=1, norm=1, beta=1.0, alpha=0.1)
         pk.pie_sweep(O, P, scan, A, prm, order=torch.from_numpy(ordr).cuda())
         # the oracle takes the valid entries, in order, as a scan of their own
@@ -150,13 +155,12 @@ def test_noise_free_fixed_point(pk, tiny):
     # the true object and probe are a fixed point of the full-window step
     print("fft pie fixed point", flush=True)
     n = tiny["probe"].shape[0]
-    amp = workloads.crop_amplitudes(tiny["intensity"], n)
+    A, amp = amps(pk, tiny["intensity"], n)
     scan = pk.Scan(tiny["pos"], tiny["obj"].shape, n, n, method="fft")
     O = torch.from_numpy(tiny["obj"].astype(np.complex64)).cuda()
     P = torch.from_numpy(tiny["probe"].astype(np.complex64)).cuda()
     O0 = O.clone()
-    pk.pie_sweep(O, P, scan, torch.from_numpy(amp.astype(np.float32)).cuda(),
-                 pk.PieParams(batch=64, norm=1, beta=1.0, alpha=1e-3))
+    pk.pie_sweep(O, P, scan, A, pk.PieParams(batch=64, norm=1, beta=1.0, alpha=1e-3))
     assert rel(O.cpu().numpy(), O0.cpu().numpy()) <= 1e-6
 
 
@@ -165,14 +169,14 @@ def test_phase2_at_scale_fft_matches_dense_and_oracle(pk):
     # 128^2 probe, 900 positions, m = n = 128, fully batched, normalised)
     print("fft pie at scale", flush=True)
     case = workloads.pie_at_scale()
-    amp = workloads.crop_amplitudes(case["intensity"], 128)
+    A, amp = amps(pk, case["intensity"], 128)
     prm = dict(batch=900, norm=1, beta=1.0, alpha=1e-3)
     outs = {}
     for method in ("fft", "dense"):
         scan = pk.Scan(case["pos"], (1024, 1024), 128, 128, method=method)
         O = torch.from_numpy(case["init"]).cuda()
         P = torch.from_numpy(case["probe"]).cuda()
-        st = pk.pie_sweep(O, P, scan, torch.from_numpy(amp).cuda(), pk.PieParams(**prm)).cpu().numpy()
+        st = pk.pie_sweep(O, P, scan, A, pk.PieParams(**prm)).cpu().numpy()
         outs[method] = (O.cpu().numpy(), st)
     assert rel(outs["fft"][0], outs["dense"][0]) <= 5e-6
     Or, _, sr = opie.pie_sweep(case["init"], case["probe"], case["pos"], amp, 128, **prm)

@@ -64,10 +64,19 @@ def test_gradient_scale_and_object_only(pk):
     assert rel(Og.grad.cpu().numpy(), 2.5 * gOr) <= 1e-4
 
 
-def test_full_workload_loss_and_gradient(pk):
+@pytest.fixture(scope="module")
+def full_case():
+    """The full loss workload (1024 positions, 256^2 patches, m = 64 on a
+    2304^2 object) with its FP64 oracle loss and gradients, computed once."""
+    case = workloads.amp_loss_case()
+    Lr, gOr, gPr = oloss.amp_loss_grad(case["obj"], case["probe"], case["pos"], case["amp"], 64)
+    return case, Lr, gOr, gPr
+
+
+def test_full_workload_loss_and_gradient(pk, full_case):
     """1024 positions, 256^2 patches, m = 64 on a 2304^2 object."""
     print("loss full workload", flush=True)
-    case = workloads.amp_loss_case()
+    case, Lr, gOr, gPr = full_case
     O, P, A = to_dev(case)
     scan = pk.Scan(case["pos"], O.shape, 256, 64)
     u = torch.empty(1024, 64, 64, dtype=torch.complex64, device="cuda")
@@ -75,7 +84,6 @@ def test_full_workload_loss_and_gradient(pk):
     gO, gP = pk.amp_loss_grad(O, P, scan, A, saved_u=u)
     gO2, gP2 = pk.amp_loss_grad(O, P, scan, A)      # recompute path
     torch.cuda.synchronize()
-    Lr, gOr, gPr = oloss.amp_loss_grad(case["obj"], case["probe"], case["pos"], case["amp"], 64)
     assert abs(L.item() - Lr) <= 1e-5 * Lr
     assert rel(gO.cpu().numpy(), gOr) <= 1e-4
     assert rel(gP.cpu().numpy(), gPr) <= 1e-4
@@ -105,3 +113,44 @@ def test_split_precision_loss_and_gradient(pk, precision, tol):
     assert abs(L.item() - Lr) <= tol * Lr
     assert rel(gO.cpu().numpy(), gOr) <= tol
     assert rel(gP.cpu().numpy(), gPr) <= tol
+
+
+@pytest.mark.parametrize("precision,tol_l,tol_g", [("split_bf16", 1e-4, 1e-3), ("split_fp16", 1e-5, 1e-4)])
+def test_full_workload_split_precision(pk, full_case, precision, tol_l, tol_g):
+    """The full loss workload in the split precisions, stored and recomputed
+    spectra, against the FP64 oracle (loss and both gradients)."""
+    print("loss full workload", precision, flush=True)
+    case, Lr, gOr, gPr = full_case
+    O, P, A = to_dev(case)
+    scan = pk.Scan(case["pos"], O.shape, 256, 64, precision=precision)
+    u = torch.empty(1024, 64, 64, dtype=torch.complex64, device="cuda")
+    L = pk.amp_loss(O, P, scan, A, saved_u=u)
+    gO, gP = pk.amp_loss_grad(O, P, scan, A, saved_u=u)
+    gO2, gP2 = pk.amp_loss_grad(O, P, scan, A)
+    torch.cuda.synchronize()
+    assert abs(L.item() - Lr) <= tol_l * Lr
+    for g, r in ((gO, gOr), (gP, gPr), (gO2, gOr), (gP2, gPr)):
+        assert rel(g.cpu().numpy(), r) <= tol_g
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("split_bf16", 1e-3), ("split_fp16", 1e-4)])
+def test_zero_exit_wave_has_zero_subgradient(pk, precision, tol):
+    """A window of zero object gives u = 0 exactly: its residual term uses
+    sgn(0) = 0, so R_j = 2 F^H u F = 0 there and the position adds a^2 to the
+    loss and nothing to the gradients; the rest match the oracle."""
+    print("loss zero window", precision, flush=True)
+    case = workloads.amp_loss_case(**SMALL)
+    obj = case["obj"].copy()
+    r, c = case["pos"][5]
+    obj[r:r + 64, c:c + 64] = 0      # windows of this scan do not overlap
+    O = torch.from_numpy(obj).cuda()
+    P = torch.from_numpy(case["probe"]).cuda()
+    A = torch.from_numpy(case["amp"]).cuda()
+    scan = pk.Scan(case["pos"], O.shape, 64, 16, precision=precision)
+    L = pk.amp_loss(O, P, scan, A)
+    gO, gP = pk.amp_loss_grad(O, P, scan, A)
+    Lr, gOr, gPr = oloss.amp_loss_grad(obj, case["probe"], case["pos"], case["amp"], 16)
+    assert abs(L.item() - Lr) <= tol * Lr
+    assert rel(gO.cpu().numpy(), gOr) <= tol
+    assert rel(gP.cpu().numpy(), gPr) <= tol
+    assert np.all(np.isfinite(gO.cpu().numpy())) and np.all(np.isfinite(gP.cpu().numpy()))

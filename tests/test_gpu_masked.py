@@ -1,5 +1,5 @@
 """GPU parity of the masked-field form (a DFT period larger than the window,
-the large non-blind experiment of Sec. 4.2) against the FP64 oracle.
+the large non-blind experiment of Sec. 4.1.3) against the FP64 oracle.
 
 Small instances (a 512^2 field, 256^2 windows, m = 64, 9 positions) run every
 chunk mode; with few positions per chunk the dense forward splits each

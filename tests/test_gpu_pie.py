@@ -37,12 +37,19 @@ def tiny():
     return workloads.tiny_pie()
 
 
+def amps(pk, intensity, m):
+    """Each side crops the data itself (Algorithm 3): the library's crop
+    kernel on the device, the oracle's crop in float64 on the host."""
+    dev = pk.crop_amplitudes(torch.from_numpy(intensity).cuda(), m)
+    return dev, opie.amplitudes(intensity, m)
+
+
 def run_gpu(pk, case, obj0, probe0, amp, m, params, order=None, sweeps=1, precision="fp32"):
     n = case["probe"].shape[0]
     scan = pk.Scan(case["pos"], obj0.shape, n, m, precision=precision)
     O = torch.from_numpy(obj0.astype(np.complex64)).cuda()
     P = torch.from_numpy(probe0.astype(np.complex64)).cuda()
-    A = torch.from_numpy(amp.astype(np.float32)).cuda()
+    A = amp if torch.is_tensor(amp) else torch.from_numpy(amp.astype(np.float32)).cuda()
     ordt = None if order is None else torch.from_numpy(np.asarray(order, dtype=np.int32)).cuda()
     stats = []
     for _ in range(sweeps):
@@ -66,8 +73,9 @@ def test_one_sweep_matches_oracle(pk, tiny, mode):
     m = tiny["m"]
     init = tiny["init"]
     P0 = tiny["probe"] * (1.0 + 0.05j) if mode.get("gamma", 0) else tiny["probe"]
-    O, P, st = run_gpu(pk, tiny, init, P0, tiny["amp"], m, pk.PieParams(**mode))
-    Or, Pr, sr = opie.pie_sweep(init, P0, tiny["pos"], tiny["amp"], m, **mode)
+    A, amp = amps(pk, tiny["intensity"], m)
+    O, P, st = run_gpu(pk, tiny, init, P0, A, m, pk.PieParams(**mode))
+    Or, Pr, sr = opie.pie_sweep(init, P0, tiny["pos"], amp, m, **mode)
     assert rel(O, Or) <= 1e-5
     if mode.get("gamma", 0):
         assert rel(P, Pr) <= 1e-5
@@ -81,11 +89,12 @@ def test_one_sweep_matches_oracle(pk, tiny, mode):
 def test_tiny_workload_ten_sweeps(pk, tiny, batch, norm):
     m = tiny["m"]
     params = dict(batch=batch, norm=norm, beta=1.0, gamma=0.0, alpha=1e-3)
-    O, _, st = run_gpu(pk, tiny, tiny["init"], tiny["probe"], tiny["amp"], m, pk.PieParams(**params), sweeps=10)
+    A, amp = amps(pk, tiny["intensity"], m)
+    O, _, st = run_gpu(pk, tiny, tiny["init"], tiny["probe"], A, m, pk.PieParams(**params), sweeps=10)
     Or = tiny["init"]
     phis = []
     for _ in range(10):
-        Or, _, s = opie.pie_sweep(Or, tiny["probe"], tiny["pos"], tiny["amp"], m, **params)
+        Or, _, s = opie.pie_sweep(Or, tiny["probe"], tiny["pos"], amp, m, **params)
         phis.append(s[0])
     assert rel(O, Or) <= 1e-4
     for a, b in zip(st, phis):
@@ -95,18 +104,19 @@ def test_tiny_workload_ten_sweeps(pk, tiny, batch, norm):
 def test_permuted_order_matches_oracle(pk, tiny):
     m = tiny["m"]
     perm = np.random.default_rng(5).permutation(64)
+    A, amp = amps(pk, tiny["intensity"], m)
     for params in (dict(batch=1, norm=0, beta=1.0), dict(batch=9, norm=1, beta=1.0, alpha=1e-3)):
-        O, _, _ = run_gpu(pk, tiny, tiny["init"], tiny["probe"], tiny["amp"], m, pk.PieParams(**params),
+        O, _, _ = run_gpu(pk, tiny, tiny["init"], tiny["probe"], A, m, pk.PieParams(**params),
                           order=perm)
-        Or, _, _ = opie.pie_sweep(tiny["init"], tiny["probe"], tiny["pos"], tiny["amp"], m, order=perm, **params)
+        Or, _, _ = opie.pie_sweep(tiny["init"], tiny["probe"], tiny["pos"], amp, m, order=perm, **params)
         assert rel(O, Or) <= 1e-5
 
 
 @pytest.mark.parametrize("m,batch,norm,gamma", [(16, 1, 0, 0.0), (16, 64, 1, 0.0), (32, 64, 1, 0.5),
                                                 (8, 5, 0, 0.2)])
 def test_noise_free_fixed_point(pk, tiny, m, batch, norm, gamma):
-    amp = workloads.crop_amplitudes(tiny["intensity"], m)
-    O, P, st = run_gpu(pk, tiny, tiny["obj"], tiny["probe"], amp, m,
+    A, amp = amps(pk, tiny["intensity"], m)
+    O, P, st = run_gpu(pk, tiny, tiny["obj"], tiny["probe"], A, m,
                        pk.PieParams(batch=batch, norm=norm, beta=1.0, gamma=gamma))
     assert rel(O, tiny["obj"]) <= 1e-6
     assert rel(P, tiny["probe"]) <= 1e-6
@@ -127,9 +137,9 @@ def test_at_scale_one_sweep(pk):
     overlap-normalised; one sweep from the random initial guess."""
     case = workloads.pie_at_scale()
     m = case["m"]
-    amp = workloads.crop_amplitudes(case["intensity"], m)
+    A, amp = amps(pk, case["intensity"], m)
     params = dict(batch=900, norm=1, beta=1.0, gamma=0.0, alpha=1e-3)
-    O, _, st = run_gpu(pk, case, case["init"], case["probe"], amp, m, pk.PieParams(**params))
+    O, _, st = run_gpu(pk, case, case["init"], case["probe"], A, m, pk.PieParams(**params))
     Or, _, sr = opie.pie_sweep(case["init"], case["probe"], case["pos"], amp, m, **params)
     assert rel(O, Or) <= 1e-5
     assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
@@ -175,9 +185,102 @@ def test_split_precision_sweeps(pk, tiny, precision, tol):
     for mode in (dict(batch=1, norm=0, beta=1.0), dict(batch=64, norm=1, beta=1.0, alpha=1e-3),
                  dict(batch=8, norm=1, beta=0.8, gamma=0.5, alpha=1e-3)):
         P0 = tiny["probe"] * (1.0 + 0.05j) if mode.get("gamma", 0) else tiny["probe"]
-        O, P, st = run_gpu(pk, tiny, tiny["init"], P0, tiny["amp"], m, pk.PieParams(**mode),
+        A, amp = amps(pk, tiny["intensity"], m)
+        O, P, st = run_gpu(pk, tiny, tiny["init"], P0, A, m, pk.PieParams(**mode),
                            precision=precision)
-        Or, Pr, sr = opie.pie_sweep(tiny["init"], P0, tiny["pos"], tiny["amp"], m, **mode)
+        Or, Pr, sr = opie.pie_sweep(tiny["init"], P0, tiny["pos"], amp, m, **mode)
         assert rel(O, Or) <= tol
         assert rel(P, Pr) <= tol
         assert abs(st[0][0] - sr[0]) <= tol * sr[0]
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-4), ("split_fp16", 1e-5)])
+def test_at_scale_one_sweep_split(pk, precision, tol):
+    """The phase-1 sweep of the warm-started workload (900 positions, 128^2
+    probe, m = 32, fully batched, overlap-normalised) in the split
+    precisions: the launch configuration the benchmark times."""
+    print("pie at scale", precision, flush=True)
+    case = workloads.pie_at_scale()
+    m = case["m"]
+    A, amp = amps(pk, case["intensity"], m)
+    params = dict(batch=900, norm=1, beta=1.0, gamma=0.0, alpha=1e-3)
+    O, _, st = run_gpu(pk, case, case["init"], case["probe"], A, m, pk.PieParams(**params),
+                       precision=precision)
+    Or, _, sr = opie.pie_sweep(case["init"], case["probe"], case["pos"], amp, m, **params)
+    assert rel(O, Or) <= tol
+    assert abs(st[0][0] - sr[0]) <= tol * sr[0]
+
+
+@pytest.mark.parametrize("params", [dict(batch=9, norm=1, beta=1.0, alpha=1e-3),
+                                    dict(batch=64, norm=0, beta=0.05),
+                                    dict(batch=5, norm=1, beta=0.8, gamma=0.5, alpha=1e-3)],
+                         ids=["b9-norm", "b64-plain", "b5-probe"])
+def test_order_with_missing_position_reuses_workspace(pk, tiny, params):
+    """A sweep with a full permutation leaves every rank in the workspace;
+    a second sweep over the same workspace whose order drops one position
+    (an entry outside [0, J)) must not gather any stale slot: the dropped
+    position contributes nothing and the chunks keep their places."""
+    print("pie order missing", params, flush=True)
+    m = tiny["m"]
+    J = len(tiny["pos"])
+    A, amp = amps(pk, tiny["intensity"], m)
+    perm = np.random.default_rng(9).permutation(J).astype(np.int32)
+    bad = perm.copy()
+    bad[11] = J + 7
+    n = tiny["probe"].shape[0]
+    scan = pk.Scan(tiny["pos"], tiny["init"].shape, n, m)
+    prm = pk.PieParams(**params)
+    ws = torch.empty(scan.workspace_bytes(prm), dtype=torch.uint8, device="cuda")
+    P0 = tiny["probe"] * (1.0 + 0.05j) if params.get("gamma", 0) else tiny["probe"]
+    O = torch.from_numpy(tiny["init"]).cuda()
+    P = torch.from_numpy(P0.astype(np.complex64)).cuda()
+    pk.pie_sweep(O, P, scan, A, prm, order=torch.from_numpy(perm).cuda(), workspace=ws)
+    O = torch.from_numpy(tiny["init"]).cuda()
+    P = torch.from_numpy(P0.astype(np.complex64)).cuda()
+    pk.pie_sweep(O, P, scan, A, prm, order=torch.from_numpy(bad).cuda(), workspace=ws)
+    Or, Pr, _ = opie.pie_sweep(tiny["init"], P0, tiny["pos"], amp, m, order=bad, **params)
+    assert rel(O.cpu().numpy(), Or) <= 1e-5
+    assert rel(P.cpu().numpy(), Pr) <= 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("split_bf16", 1e-4), ("split_fp16", 1e-5)])
+def test_zero_exit_wave_projects_to_the_amplitude(pk, tiny, precision, tol):
+    """A window of zero object gives u = 0 exactly; the projection then takes
+    theta(0) = 0, i.e. u' = a (real), in every precision."""
+    print("pie zero window", precision, flush=True)
+    m = tiny["m"]
+    n = tiny["probe"].shape[0]
+    A, amp = amps(pk, tiny["intensity"], m)
+    init = tiny["init"].copy()
+    r, c = tiny["pos"][0]
+    init[r:r + n, c:c + n] = 0
+    params = dict(batch=64, norm=1, beta=1.0, alpha=1e-3)
+    O, _, st = run_gpu(pk, tiny, init, tiny["probe"], A, m, pk.PieParams(**params), precision=precision)
+    Or, _, sr = opie.pie_sweep(init, tiny["probe"], tiny["pos"], amp, m, **params)
+    assert rel(O, Or) <= tol
+    assert abs(st[0][0] - sr[0]) <= tol * sr[0]
+    # the zero window moved to a non-zero estimate
+    assert np.linalg.norm(O[r:r + n, c:c + n]) > 0
+
+
+def test_sequential_overlap_normalised_dense(pk, tiny):
+    """batch = 1 with the overlap-normalised step on the dense contraction.
+    alpha = 0.1: at alpha = 1e-3 the per-pixel step 1/(|P|^2 + alpha max)
+    reaches 1000 on the probe's tails and sixty-four chained FP32 steps
+    amplify rounding far beyond the transform's error (the iterate itself
+    is ill-conditioned there, in any arithmetic)."""
+    m = tiny["m"]
+    A, amp = amps(pk, tiny["intensity"], m)
+    params = dict(batch=1, norm=1, beta=1.0, alpha=0.1)
+    O, _, st = run_gpu(pk, tiny, tiny["init"], tiny["probe"], A, m, pk.PieParams(**params))
+    Or, _, sr = opie.pie_sweep(tiny["init"], tiny["probe"], tiny["pos"], amp, m, **params)
+    assert rel(O, Or) <= 1e-5
+    assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-4), ("split_fp16", 1e-6)])
+def test_noise_free_fixed_point_split(pk, tiny, precision, tol):
+    A, amp = amps(pk, tiny["intensity"], tiny["m"])
+    O, _, _ = run_gpu(pk, tiny, tiny["obj"], tiny["probe"], A, tiny["m"],
+                      pk.PieParams(batch=64, norm=1, beta=1.0, alpha=1e-3), precision=precision)
+    assert rel(O, tiny["obj"]) <= tol

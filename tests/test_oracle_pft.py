@@ -195,7 +195,7 @@ def test_plausible_mistakes_are_caught():
     assert rel(Fo @ psi @ Fo.T, ref) > 0.5          # window off by one
 
 
-# --- masked full field: DFT period larger than the window (Sec. 4.2) -------
+# --- masked full field: DFT period larger than the window (Sec. 4.1.3) -------
 
 @pytest.mark.parametrize("n,N,m,shift", [(8, 24, 10, (5, 11)), (6, 16, 7, (0, 9)), (12, 12, 5, (0, 0))])
 def test_period_forward_equals_crop_of_zero_padded_field_fft(n, N, m, shift):

@@ -229,6 +229,91 @@ def test_overlap_normalised_update_leaves_unlit_pixels():
     assert abs(pie.rel_change(st) - np.linalg.norm(O - z0) / np.linalg.norm(z0)) < 1e-14
 
 
+def _doubled_amplitudes(obj, probe, pos):
+    """Full-window amplitudes twice the current model's, |fft2(P O_j)| in
+    centred order via NumPy's FFT: at m = n the projection then doubles
+    every coefficient, so the correction of eq. (3) is the exit wave itself
+    (the pseudo-inverse of the whole spectrum is the inverse DFT)."""
+    n = probe.shape[0]
+    return np.stack([2.0 * np.abs(np.fft.fftshift(np.fft.fft2(probe * obj[r:r + n, c:c + n])))
+                     for r, c in pos])
+
+
+@pytest.mark.parametrize("alpha", [1e-3, 0.25])
+def test_batched_overlap_normalised_step_closed_form(alpha):
+    """One chunk of overlapping positions, overlap-normalised, with a probe
+    step.  With amplitudes twice the model's at m = n the correction of
+    position j is psi_j = P O_j, so numO = sum_j |P|^2 O = D O pixel by
+    pixel and numP = P E: the step must be
+        O' = O (1 + beta D / (D + alpha max D)),
+        P' = P (1 + gamma E / (E + alpha max E)),
+    with D, E the summed |P|^2 and |O_j|^2.  A denominator of sum |P| (or
+    |P| sums squared), a missing conjugate, or a regulariser without the
+    maximum each break it."""
+    rs = np.random.default_rng(21)
+    H, n = 20, 8
+    obj = rs.uniform(0.3, 1.2, (H, H)) * np.exp(1j * rs.uniform(-2, 2, (H, H)))
+    probe = rs.uniform(0.1, 1.5, (n, n)) * np.exp(1j * rs.uniform(-2, 2, (n, n)))
+    # two windows sharing a 5 x 5 corner, a third overlapping both, one apart
+    pos = np.array([[0, 0], [3, 3], [6, 1], [12, 12]])
+    amp = _doubled_amplitudes(obj, probe, pos)
+    beta, gamma = 0.7, 0.4
+    O, P, _ = pie.pie_sweep(obj, probe, pos, amp, n, batch=len(pos), norm=1,
+                            beta=beta, gamma=gamma, alpha=alpha)
+    D = np.zeros((H, H))
+    E = np.zeros((n, n))
+    for r, c in pos:
+        D[r:r + n, c:c + n] += np.abs(probe) ** 2
+        E += np.abs(obj[r:r + n, c:c + n]) ** 2
+    O_ref = obj * (1.0 + beta * D / (D + alpha * D.max()))
+    P_ref = probe * (1.0 + gamma * E / (E + alpha * E.max()))
+    assert np.max(np.abs(O - O_ref)) <= 1e-12 * np.max(np.abs(obj))
+    assert np.max(np.abs(P - P_ref)) <= 1e-12 * np.max(np.abs(probe))
+    # the overlap is real: some pixel is lit by three windows
+    cover = np.zeros((H, H), int)
+    for r, c in pos:
+        cover[r:r + n, c:c + n] += 1
+    assert cover.max() == 3
+    # plausible mistakes are far from the oracle's answer: sum |P| as the
+    # denominator, the regulariser without max D, and conj dropped (the
+    # numerator then sums P^2 O instead of |P|^2 O)
+    Dabs = np.zeros((H, H))
+    S2 = np.zeros((H, H), complex)
+    for r, c in pos:
+        Dabs[r:r + n, c:c + n] += np.abs(probe)
+        S2[r:r + n, c:c + n] += probe ** 2
+    for wrong in (obj * (1.0 + beta * D / (Dabs + alpha * Dabs.max())),
+                  obj * (1.0 + beta * D / (D + alpha)),
+                  obj * (1.0 + beta * S2 / (D + alpha * D.max()))):
+        assert np.linalg.norm(wrong - O) > 1e-3 * np.linalg.norm(O)
+
+
+def test_order_entries_outside_the_scan_contribute_nothing():
+    """An order entry outside range(J) keeps its place in its chunk and adds
+    nothing: chunks of (a, bad, b) equal chunks of (a, b) when the chunk
+    boundaries fall the same way."""
+    obj, probe, pos, inten = small_case(14)
+    amp = pie.amplitudes(inten, 8)
+    J = len(pos)
+    perm = np.random.default_rng(4).permutation(J)
+    bad = perm.copy()
+    bad[2] = J + 5
+    z0 = obj * 0.9
+    got, _, _ = pie.pie_sweep(z0, probe, pos, amp, 8, order=bad, batch=3, norm=1)
+    # the same chunks, the bad entry's position left out of its chunk
+    keep = [j for j in bad if j < J]
+    ref = z0.astype(np.complex128)
+    chunks = [bad[k:k + 3] for k in range(0, J, 3)]
+    for ch in chunks:
+        ch = [j for j in ch if j < J]
+        ref, _, _ = pie.pie_sweep(ref, probe, pos[ch], amp[ch], 8, batch=len(ch), norm=1)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    # and the left-out position is not the same as a full permutation's result
+    full, _, _ = pie.pie_sweep(z0, probe, pos, amp, 8, order=perm, batch=3, norm=1)
+    assert np.linalg.norm(full - got) > 1e-6 * np.linalg.norm(full)
+    assert len(keep) == J - 1
+
+
 def test_rel_error_ignores_global_phase():
     z = rnd((10, 10), 11)
     assert pie.rel_error(z * np.exp(1.234j), z) < 1e-15
@@ -270,7 +355,7 @@ def test_plausible_mistakes_in_the_update_are_caught():
         assert np.linalg.norm(z - ref) / np.linalg.norm(ref) > 1e-3
 
 
-# --- masked full field (Sec. 4.2): the sweep with a DFT period ------------
+# --- masked full field (Sec. 4.1.3): the sweep with a DFT period ------------
 
 def _full_field_sweep(obj, probe, pos, amp, m, N, beta, alpha, norm):
     """The masked-field PIE iterate computed on the whole N x N field with

@@ -20,7 +20,7 @@ def crop_fft2(Z, m):
 
 
 def test_paper_constant_r13_at_eps_1e7():
-    # Sec. 4.2: m~ = p = 64 (m~/p = 1) and eps = 1e-7 give r = 13
+    # Sec. 4: m~ = p = 64 (m~/p = 1) and eps = 1e-7 give r = 13
     assert polypft.choose_r(1e-7, 1.0) == 13
     assert polypft.xi_of(1e-7, 12) < 1.0 <= polypft.xi_of(1e-7, 13)
 

@@ -103,14 +103,6 @@ def intensities(obj, probe, pos):
     return out
 
 
-def crop_amplitudes(intensity, m):
-    """sqrt of the centred m x m crop of fftshift-layout intensities (the data
-    cropping of Algorithm 3), float32 [J][m][m]."""
-    n = intensity.shape[-1]
-    s = n // 2 - m // 2
-    return np.sqrt(intensity[..., s:s + m, s:s + m].astype(np.float64)).astype(np.float32)
-
-
 def poisson(rng, intensity, photons):
     """Poisson counts with one global scale so that the mean total count per
     pattern equals ``photons``; returned rescaled to the input's units."""
@@ -138,15 +130,15 @@ def complex_normal(rng, shape):
 def tiny_pie(seed=1):
     """Plain PIE, tiny: 128^2 blob object, 32^2 Gaussian probe (sigma 6 px,
     kappa = pi/144), 8 x 8 raster step 8 from offset 20, noise-free data,
-    window m = 16."""
+    window m = 16.  The amplitudes are cropped by each side itself (the data
+    cropping of Algorithm 3 is a step of the method, not an input)."""
     rs = streams(seed)
     obj = blob_object(rs[0], 128, 128)
     probe = gaussian_probe(32, 6.0, np.pi / 144.0)
     pos = raster(8, 8, 8, 20)
     inten = intensities(obj, probe, pos)
     init = random_init(rs[4], 128, 128)
-    return dict(obj=obj, probe=probe, pos=pos, intensity=inten, m=16,
-                amp=crop_amplitudes(inten, 16), init=init)
+    return dict(obj=obj, probe=probe, pos=pos, intensity=inten, m=16, init=init)
 
 
 PFT_BLOCK = 64   # patches per seeded block of the standalone-transform batch
@@ -267,7 +259,7 @@ def adjoint_descs(desc):
 def serpentine(k, step, by_rows=False):
     """k x k window corners, column by column: down the first column, up the
     second, down the third, ... (the scan of the non-blind experiments,
-    Sec. 4.2); by_rows: along the first row to the right, back along the
+    Sec. 4.1.1); by_rows: along the first row to the right, back along the
     second, ... (the blind experiments), as (row, col) offsets [k*k][2]."""
     pos = []
     for a in range(k):
@@ -297,7 +289,7 @@ def masked_field_amplitudes(field_img, probe, pos, m, period, workers=-1):
 
 
 def masked_field(seed=6, field=16384, m=128, coarse=1024, sigma_f=24.0, amp_positions=None, with_init=True):
-    """Non-blind masked-field workload (the large experiment of Sec. 4.2):
+    """Non-blind masked-field workload (the large experiment of Sec. 4.1.3):
     a field x field pure-phase object (smooth random phase made on a
     coarse x coarse grid with sigma_f px and interpolated bilinearly),
     identity probe on field/2 x field/2 windows, 3 x 3 serpentine scan with
@@ -321,7 +313,7 @@ def masked_field(seed=6, field=16384, m=128, coarse=1024, sigma_f=24.0, amp_posi
 
 
 def circular_probe(n, radius, sigma=1e6):
-    """Circular illumination window of the blind experiments (Sec. 4.3): the
+    """Circular illumination window of the blind experiments (Sec. 4.2.1, Appendix B): the
     Gaussian exp(-r^2 / 2 sigma^2) inside a circle of `radius` px (sigma =
     1e6: flat), zero outside."""
     r2 = _radius2(n)
@@ -329,7 +321,7 @@ def circular_probe(n, radius, sigma=1e6):
 
 
 def blind_circular(seed=7, n=128, radius=58.0, shift=50, grid=4, m=32):
-    """Blind ePIE with circular windows (Sec. 4.3), scaled so the full
+    """Blind ePIE with circular windows (Sec. 4.2.3), scaled so the full
     window fits the full-resolution phase: 4 x 4 windows of n = 128 with a
     flat circular probe of radius 58 shifted by 50 px (about the paper's
     radius / shift ratio 175 / 150 and 50 % overlap), row-wise serpentine
