@@ -264,6 +264,24 @@ pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* a
                         void* workspace, size_t ws_bytes, double* stats_dev,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sweep
+ * of pie_sweep with the library's own fixed device scratch in place of the
+ * caller's workspace.  Same arguments, semantics and results as pie_sweep
+ * (the same kernels run); no call allocates.  The scratch is a static
+ * device array of PFTPIE_NOALLOC_SCRATCH_MIB MiB that every GPU the library
+ * runs on holds until the process ends; its address is looked up once per
+ * device on the first call there.  A sweep whose pie_workspace_size exceeds
+ * it returns PFTPIE_E_INVALID (use a smaller batch, or pie_sweep).  Every
+ * call on one GPU shares that GPU's scratch: calls that may overlap in time
+ * on one GPU (different streams, threads) race and must not be issued;
+ * calls in one stream are ordered and safe.  The scratch keeps the last
+ * call's contents; each sweep clears what it needs itself. */
+#define PFTPIE_NOALLOC_SCRATCH_MIB 160
+pftpie_status pie_sweep_noalloc(pie_scan scan, void* object, void* probe, const float* amp,
+                                const int32_t* order_dev, const pie_params* p, double* stats_dev,
+                                void* stream);
+
 /* Data cropping of Algorithm 3 (Sec. 3.2): amp[j] = sqrt(centred m x m crop
  * of intensity[j]).  intensity: device float32 [J][n][n] in fftshift layout
  * (zero frequency at (floor(n/2), floor(n/2))), non-negative; amp: device

@@ -62,6 +62,7 @@ SIGNATURES = {
     "pie_scan_destroy": (i32, [c_scan]),
     "pie_workspace_size": (i32, [c_scan, ctypes.POINTER(PieParams), ctypes.POINTER(sz)]),
     "pie_sweep": (i32, [c_scan, vp, vp, vp, vp, ctypes.POINTER(PieParams), vp, sz, vp, vp]),
+    "pie_sweep_noalloc": (i32, [c_scan, vp, vp, vp, vp, ctypes.POINTER(PieParams), vp, vp]),
     "pie_crop_amplitudes": (i32, [vp, i32, i32, i32, vp, vp]),
     "amp_loss_workspace_size": (i32, [c_scan, ctypes.POINTER(sz)]),
     "amp_loss_forward": (i32, [c_scan, vp, vp, vp, vp, vp, vp, sz, vp]),

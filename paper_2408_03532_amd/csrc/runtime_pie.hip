@@ -1,6 +1,7 @@
 // C ABI of the PIE sweep: scans, workspace sizing, validation, dispatch.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -9,6 +10,13 @@
 #include "pie.hpp"
 
 namespace pftpie {
+
+// Device scratch of pie_sweep_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address); it uses the address
+// hipGetSymbolAddress returns for the device, looked up once per device.
+constexpr size_t kNoAllocBytes = (size_t)PFTPIE_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -76,6 +84,112 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
   return pa < pb + nb && pb < pa + na;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on `device`, looked up with that device current.
+pftpie_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(PFTPIE_E_UNSUPPORTED, "pie_sweep_noalloc: device index");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "pie_sweep_noalloc: hipGetDevice");
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "pie_sweep_noalloc: hipSetDevice");
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "pie_sweep_noalloc: hipGetSymbolAddress");
+    if (!p || (uintptr_t)p % 256) return fail(PFTPIE_E_DEVICE, "pie_sweep_noalloc: scratch address unusable");
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return PFTPIE_OK;
+}
+
+// Body of pie_sweep and pie_sweep_noalloc: validation, then the launches.
+pftpie_status sweep(pie_scan scan, void* object, void* probe, const float* amp, const int32_t* order_dev,
+                    const pie_params* p, void* workspace, size_t ws_bytes, double* stats_dev, void* stream,
+                    const char* who) {
+  if (pftpie_status st = check_params(scan, p)) return st;
+  const std::string name(who);
+  if (!object || !probe || !amp) return fail(PFTPIE_E_INVALID, name + ": NULL object, probe or amplitudes");
+  if ((uintptr_t)object % 8 || (uintptr_t)probe % 8 || (uintptr_t)amp % 4)
+    return fail(PFTPIE_E_INVALID, name + ": misaligned object, probe or amplitudes");
+  if (order_dev && (uintptr_t)order_dev % 4) return fail(PFTPIE_E_INVALID, name + ": misaligned order");
+  if (stats_dev && (uintptr_t)stats_dev % 8) return fail(PFTPIE_E_INVALID, name + ": misaligned stats");
+  const pftpie_plan_s* pl = scan->plan;
+  const int batch = p->batch < scan->J ? p->batch : scan->J;
+  const int probe_step = p->gamma > 0.f;
+  const PieLayout L = pie_layout(scan, batch, p->norm, probe_step);
+  if (!workspace || ws_bytes < L.total)
+    return fail(PFTPIE_E_INVALID, name + ": workspace smaller than pie_workspace_size (" +
+                                      std::to_string(L.total) + " bytes)");
+  if ((uintptr_t)workspace % 256) return fail(PFTPIE_E_INVALID, name + ": workspace must be 256-byte aligned");
+  const size_t ob = (size_t)scan->H * scan->W * 8, pb = (size_t)pl->n * pl->n * 8;
+  const size_t ab = (size_t)scan->J * pl->m * pl->m * 4;
+  if (overlaps(object, ob, probe, pb) || overlaps(object, ob, workspace, L.total) ||
+      overlaps(probe, pb, workspace, L.total) || overlaps(amp, ab, object, ob) || overlaps(amp, ab, probe, pb) ||
+      overlaps(amp, ab, workspace, L.total))
+    return fail(PFTPIE_E_INVALID, name + ": object, probe, amplitudes and workspace must not overlap");
+  char* ws = static_cast<char*>(workspace);
+  auto at = [&](size_t off) -> void* { return off == SIZE_MAX ? nullptr : ws + off; };
+  PieArgs a{};
+  a.n = pl->n;
+  a.m = pl->m;
+  a.nb = pl->nb;
+  a.mt = pl->mt;
+  a.J = scan->J;
+  a.H = scan->H;
+  a.W = scan->W;
+  a.bb_r0 = scan->bb_r0;
+  a.bb_c0 = scan->bb_c0;
+  a.bb_h = scan->bb_h;
+  a.bb_w = scan->bb_w;
+  a.tiles_x = scan->tiles_x;
+  a.tiles_y = scan->tiles_y;
+  a.pos = scan->pos;
+  a.order = order_dev;
+  a.tile_ptr = scan->tile_ptr;
+  a.tile_pos = scan->tile_pos;
+  a.fa = pl->fa;
+  a.ft = pl->ft;
+  a.fft_tw = pl->method == PFTPIE_METHOD_FFT ? static_cast<const float2*>(pl->fft_tw) : nullptr;
+  a.prec = pl->prec;
+  a.period = pl->period;
+  a.inv_n2 = (float)(1.0 / ((double)pl->period * pl->period));
+  a.norm = p->norm;
+  a.probe_step = probe_step;
+  a.probe_literal = probe_step && p->probe_update == 1;
+  a.probe_pass = 0;
+  a.beta = p->beta;
+  a.gamma = p->gamma;
+  a.alpha = p->alpha;
+  a.O = static_cast<float2*>(object);
+  a.P = static_cast<float2*>(probe);
+  a.amp = amp;
+  a.R = static_cast<float2*>(at(L.R));
+  a.part = static_cast<float2*>(at(L.part));
+  a.splits = L.splits;
+  a.num_cu = pl->num_cu;
+  a.dpsi = static_cast<float2*>(at(L.dpsi));
+  a.phi_part = static_cast<double*>(at(L.phi));
+  a.rank = static_cast<int32_t*>(at(L.rank));
+  a.winmax = static_cast<unsigned*>(at(L.winmax));
+  a.O0 = static_cast<float2*>(at(L.O0));
+  a.numO = static_cast<float2*>(at(L.numO));
+  a.D = static_cast<double*>(at(L.D));
+  a.numP = static_cast<float2*>(at(L.numP));
+  a.E = static_cast<double*>(at(L.E));
+  a.maxpart = static_cast<double*>(at(L.maxpart));
+  a.maxes = static_cast<double*>(at(L.maxes));
+  a.red = static_cast<double*>(at(L.red));
+  a.stats = stats_dev ? stats_dev : static_cast<double*>(at(L.stats));
+  hipError_t e = launch_pie_sweep(a, batch, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PFTPIE_OK : hip_fail(e, (name + ": launch").c_str());
 }
 
 }  // namespace
@@ -191,81 +305,21 @@ pftpie_status pie_workspace_size(pie_scan scan, const pie_params* p, size_t* byt
 
 pftpie_status pie_sweep(pie_scan scan, void* object, void* probe, const float* amp, const int32_t* order_dev,
                         const pie_params* p, void* workspace, size_t ws_bytes, double* stats_dev, void* stream) {
+  return sweep(scan, object, probe, amp, order_dev, p, workspace, ws_bytes, stats_dev, stream, "pie_sweep");
+}
+
+pftpie_status pie_sweep_noalloc(pie_scan scan, void* object, void* probe, const float* amp,
+                                const int32_t* order_dev, const pie_params* p, double* stats_dev, void* stream) {
   if (pftpie_status st = check_params(scan, p)) return st;
-  if (!object || !probe || !amp) return fail(PFTPIE_E_INVALID, "pie_sweep: NULL object, probe or amplitudes");
-  if ((uintptr_t)object % 8 || (uintptr_t)probe % 8 || (uintptr_t)amp % 4)
-    return fail(PFTPIE_E_INVALID, "pie_sweep: misaligned object, probe or amplitudes");
-  if (order_dev && (uintptr_t)order_dev % 4) return fail(PFTPIE_E_INVALID, "pie_sweep: misaligned order");
-  if (stats_dev && (uintptr_t)stats_dev % 8) return fail(PFTPIE_E_INVALID, "pie_sweep: misaligned stats");
-  const pftpie_plan_s* pl = scan->plan;
   const int batch = p->batch < scan->J ? p->batch : scan->J;
-  const int probe_step = p->gamma > 0.f;
-  const PieLayout L = pie_layout(scan, batch, p->norm, probe_step);
-  if (!workspace || ws_bytes < L.total)
-    return fail(PFTPIE_E_INVALID, "pie_sweep: workspace smaller than pie_workspace_size (" +
-                                      std::to_string(L.total) + " bytes)");
-  if ((uintptr_t)workspace % 256) return fail(PFTPIE_E_INVALID, "pie_sweep: workspace must be 256-byte aligned");
-  const size_t ob = (size_t)scan->H * scan->W * 8, pb = (size_t)pl->n * pl->n * 8;
-  const size_t ab = (size_t)scan->J * pl->m * pl->m * 4;
-  if (overlaps(object, ob, probe, pb) || overlaps(object, ob, workspace, L.total) ||
-      overlaps(probe, pb, workspace, L.total) || overlaps(amp, ab, object, ob) || overlaps(amp, ab, probe, pb) ||
-      overlaps(amp, ab, workspace, L.total))
-    return fail(PFTPIE_E_INVALID, "pie_sweep: object, probe, amplitudes and workspace must not overlap");
-  char* ws = static_cast<char*>(workspace);
-  auto at = [&](size_t off) -> void* { return off == SIZE_MAX ? nullptr : ws + off; };
-  PieArgs a{};
-  a.n = pl->n;
-  a.m = pl->m;
-  a.nb = pl->nb;
-  a.mt = pl->mt;
-  a.J = scan->J;
-  a.H = scan->H;
-  a.W = scan->W;
-  a.bb_r0 = scan->bb_r0;
-  a.bb_c0 = scan->bb_c0;
-  a.bb_h = scan->bb_h;
-  a.bb_w = scan->bb_w;
-  a.tiles_x = scan->tiles_x;
-  a.tiles_y = scan->tiles_y;
-  a.pos = scan->pos;
-  a.order = order_dev;
-  a.tile_ptr = scan->tile_ptr;
-  a.tile_pos = scan->tile_pos;
-  a.fa = pl->fa;
-  a.ft = pl->ft;
-  a.fft_tw = pl->method == PFTPIE_METHOD_FFT ? static_cast<const float2*>(pl->fft_tw) : nullptr;
-  a.prec = pl->prec;
-  a.period = pl->period;
-  a.inv_n2 = (float)(1.0 / ((double)pl->period * pl->period));
-  a.norm = p->norm;
-  a.probe_step = probe_step;
-  a.probe_literal = probe_step && p->probe_update == 1;
-  a.probe_pass = 0;
-  a.beta = p->beta;
-  a.gamma = p->gamma;
-  a.alpha = p->alpha;
-  a.O = static_cast<float2*>(object);
-  a.P = static_cast<float2*>(probe);
-  a.amp = amp;
-  a.R = static_cast<float2*>(at(L.R));
-  a.part = static_cast<float2*>(at(L.part));
-  a.splits = L.splits;
-  a.num_cu = pl->num_cu;
-  a.dpsi = static_cast<float2*>(at(L.dpsi));
-  a.phi_part = static_cast<double*>(at(L.phi));
-  a.rank = static_cast<int32_t*>(at(L.rank));
-  a.winmax = static_cast<unsigned*>(at(L.winmax));
-  a.O0 = static_cast<float2*>(at(L.O0));
-  a.numO = static_cast<float2*>(at(L.numO));
-  a.D = static_cast<double*>(at(L.D));
-  a.numP = static_cast<float2*>(at(L.numP));
-  a.E = static_cast<double*>(at(L.E));
-  a.maxpart = static_cast<double*>(at(L.maxpart));
-  a.maxes = static_cast<double*>(at(L.maxes));
-  a.red = static_cast<double*>(at(L.red));
-  a.stats = stats_dev ? stats_dev : static_cast<double*>(at(L.stats));
-  hipError_t e = launch_pie_sweep(a, batch, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "pie_sweep: launch");
+  const size_t need = pie_layout(scan, batch, p->norm, p->gamma > 0.f).total;
+  if (need > kNoAllocBytes)
+    return fail(PFTPIE_E_INVALID, "pie_sweep_noalloc: this sweep needs " + std::to_string(need) +
+                                      " bytes of workspace, above the library's fixed scratch of " +
+                                      std::to_string(kNoAllocBytes) + " bytes (use a smaller batch or pie_sweep)");
+  void* ws = nullptr;
+  if (pftpie_status st = scratch_address(scan->plan->device, &ws)) return st;
+  return sweep(scan, object, probe, amp, order_dev, p, ws, kNoAllocBytes, stats_dev, stream, "pie_sweep_noalloc");
 }
 
 pftpie_status pie_crop_amplitudes(const float* intensity, int32_t J, int32_t n, int32_t m, float* amp,
