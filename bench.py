@@ -261,6 +261,85 @@ def loss_rate(torch, pk, precision="fp32", steps=5, warmup=1):
             "fwd_bwd_tflops_alg": 2 * flops / ((f + b) * 1e-3) / 1e12, "precision": precision}
 
 
+ERR_LEVELS = (0.5, 0.3, 0.2, 0.15, 0.1, 0.07, 0.05, 0.03, 0.02)
+
+
+def lit_mask(pos, probe, shape, frac=0.1):
+    """Pixels whose summed probe intensity sum_j |P|^2 over the windows is at
+    least frac of its maximum: where the data constrain the object."""
+    n = probe.shape[0]
+    D = np.zeros(shape)
+    p2 = np.abs(probe.astype(np.complex128)) ** 2
+    for r, c in pos:
+        D[r:r + n, c:c + n] += p2
+    return D >= frac * D.max()
+
+
+def recon_study(torch, pk, precision="fp32", hybrid=True, iters_pft=50, iters_full=100, tol_full=5e-4,
+                case=None):
+    """Reconstruction of the warm-started workload (1024^2 phase object,
+    900 positions, Poisson data at 1e4 photons per pattern) from its random
+    initial guess, non-blind, fully batched overlap-normalised sweeps
+    (beta = 1, alpha = 1e-3).  hybrid: Algorithm 3 -- exactly iters_pft
+    partial-transform sweeps at m = 32 (in `precision`), then full-window
+    sweeps until the relative change is below tol_full or iters_full sweeps;
+    otherwise full-window sweeps only, from the same guess, for up to
+    iters_pft + iters_full sweeps.  After every sweep the relative error
+    against the true object (global phase removed, lit pixels) is evaluated
+    outside the timed region; time is the summed device time of the sweeps
+    (events on the launch stream).  Returns the error history and the sweep
+    time at which each error level of ERR_LEVELS is first reached."""
+    import workloads
+    case = case or workloads.pie_at_scale()
+    pos, n = case["pos"], case["probe"].shape[0]
+    mask = torch.from_numpy(lit_mask(pos, case["probe"], case["obj"].shape)).cuda()
+    truth = torch.from_numpy(case["obj"]).cuda()[mask].to(torch.complex128)
+    tnorm = float(torch.linalg.vector_norm(truth))
+    I = torch.from_numpy(case["intensity"]).cuda()
+    O = torch.from_numpy(case["init"]).cuda()
+    P = torch.from_numpy(case["probe"]).cuda()
+    prm = pk.PieParams(batch=len(pos), norm=1, beta=1.0, alpha=1e-3)
+    if hybrid:
+        phases = [(case["m"], precision, iters_pft, 0.0), (n, "fp32", iters_full, tol_full)]
+    else:
+        phases = [(n, "fp32", iters_pft + iters_full, tol_full)]
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    e0, e1 = ev_pair(torch)
+    t_ms, hist = 0.0, []
+
+    def error():
+        z = O[mask].to(torch.complex128)
+        ip = torch.vdot(z, truth)
+        ph = ip / ip.abs() if float(ip.abs()) > 0 else 1.0
+        return float(torch.linalg.vector_norm(z * ph - truth)) / tnorm
+
+    err0 = error()
+    for phase, (mm, prec, iters, tol) in enumerate(phases):
+        scan = pk.Scan(pos, O.shape, n, mm, precision=prec)
+        amp = pk.crop_amplitudes(I, mm)
+        for it in range(iters):
+            e0.record()
+            pk.pie_sweep(O, P, scan, amp, prm, stats=stats)
+            e1.record()
+            st = stats.cpu().numpy()
+            t_ms += e0.elapsed_time(e1)
+            rc = float(np.sqrt(st[1] / st[2])) if st[2] > 0 else float("inf")
+            hist.append((phase, it, t_ms, float(st[0]), rc, error()))
+            if rc < tol:
+                break
+        scan.close()
+    reach = {}
+    for lev in ERR_LEVELS:
+        hit = [h for h in hist if h[5] <= lev]
+        reach[str(lev)] = None if not hit else {"ms": hit[0][2], "sweep": hist.index(hit[0]) + 1}
+    return {"hybrid": hybrid, "precision_phase1": precision if hybrid else None,
+            "sweeps": [sum(1 for h in hist if h[0] == p) for p in range(len(phases))],
+            "initial_error": err0, "final_error": hist[-1][5], "best_error": min(h[5] for h in hist),
+            "total_ms": t_ms, "time_to_error": reach,
+            "history": [{"phase": h[0], "ms": round(h[2], 4), "err": round(h[5], 6), "rel_change": h[4]}
+                        for h in hist]}
+
+
 def group_rate(torch, pk, precisions, steps=5, warmup=2):
     """Uneven batch: 8192 descriptors, n in {64,128,256,512}, m = n/4, one
     persistent launch per call (graph replay).  Inputs drawn on the device
@@ -379,6 +458,11 @@ def main():
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])
         extra["amp_loss_1024x256"] = loss_rate(torch, pk)
+        import workloads
+        c3 = workloads.pie_at_scale()
+        study = {f"hybrid_{p}": recon_study(torch, pk, p, case=c3) for p in ("fp32", "split_bf16", "split_fp16")}
+        study["full_resolution_only"] = recon_study(torch, pk, "fp32", hybrid=False, case=c3)
+        extra["reconstruction_at_scale"] = study
         out["extra"] = extra
 
     if args.copy_calibration:

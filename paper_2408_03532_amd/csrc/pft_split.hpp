@@ -117,9 +117,9 @@ __device__ __forceinline__ c4 c4_of(const f32x4& re, const f32x4& im) {
 #endif
 constexpr int kSplitRing = PFTPIE_SPLIT_RING;
 template <class PR, int MT, int CT, class Src, class Tab>
-__device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab& FA, int c2t0,
-                                               f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
-                                               int sstep = 1, int rot = 0) {
+__device__ __forceinline__ void fwd_wave_split_pass(const Src& src, int NB, const Tab& FA, int c2t0,
+                                                    f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0,
+                                                    int sstep, int rot) {
   static_assert(kSplitRing % 4 == 0, "ring size must be a multiple of 4");
   // raw exit-wave operands (probe and object values, twice the registers of
   // a formed block) take half the ring depth
@@ -255,13 +255,121 @@ __device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP16 range guard.  FP16 holds magnitudes up to 65504: an operand component,
+// or a component of the stage-1 intermediate (T in the forward, S in the
+// adjoint), beyond it turns into inf when it is split, and the products then
+// leave non-finite accumulators.  The engines detect that (a wave vote over
+// the accumulators, before anything is stored), find the largest operand
+// component c of the wave's input, and run the work again on the input
+// times s = 2^e, the largest power of two with 2 K c s <= 2^15, where K is
+// the length of a stage-1 sum (each intermediate component is a sum of K
+// products with |Re|, |Im| <= 2 c |F| = 2 c).  The results are then
+// multiplied by 1/s.  Both scalings are exact (they move exponents only), so
+// a rescued patch carries the same relative error as any other.  BF16 has
+// the FP32 exponent range and needs no guard.
+template <class PR>
+constexpr bool kRangeGuard = std::is_same<PR, PrecF16>::value;
+
+constexpr float kF16Max = 65504.f;
+
+// s = 2^e, the largest power of two with 2 K c s <= 2^15; 0 when c is not
+// finite (an inf or NaN input has nothing to rescue).
+__device__ __forceinline__ float guard_scale(float c, int K) {
+  if (!(c <= 3.0e38f)) return 0.f;
+  if (c == 0.f) return 1.f;
+  int e;
+  (void)frexpf(32768.f / (2.f * (float)K * c), &e);
+  return ldexpf(1.f, e - 1);
+}
+
+__device__ __forceinline__ float absmax_c4(float acc, const c4& v) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc = fmaxf(acc, fmaxf(fabsf(v.v[i].x), fabsf(v.v[i].y)));
+  return acc;
+}
+
+// True on every lane when some lane holds a component outside [-lim, lim]
+// or a NaN.
+template <int N>
+__device__ __forceinline__ bool wave_any_beyond(const f32x4 (&re)[N], const f32x4 (&im)[N], float lim) {
+  float mx = 0.f;
+  int bad = 0;
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      mx = fmaxf(mx, fmaxf(fabsf(re[a][i]), fabsf(im[a][i])));
+      bad |= (re[a][i] != re[a][i]) | (im[a][i] != im[a][i]);
+    }
+  return __ballot(bad || !(mx <= lim)) != 0;
+}
+
+// Operand source whose values are multiplied by k (a power of two).
+template <class Src>
+struct ScaledSrc {
+  using Raw = typename RawOf<Src>::type;
+  Src s;
+  float k;
+  __device__ __forceinline__ Raw load_raw(int row, int col0) const { return ::pftpie::load_raw(s, row, col0); }
+  __device__ __forceinline__ c4 combine(const Raw& r) const {
+    c4 z = ::pftpie::combine(s, r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z.v[i] = make_float2(z.v[i].x * k, z.v[i].y * k);
+    return z;
+  }
+  __device__ __forceinline__ c4 load(int row, int col0) const { return combine(load_raw(row, col0)); }
+};
+
+// Forward, split: fwd_wave_split_pass, and for FP16 the range guard over the
+// wave's strips (K = NB * 16 terms per stage-1 sum).
+template <class PR, int MT, int CT, class Src, class Tab>
+__device__ __forceinline__ void fwd_wave_split(const Src& src, int NB, const Tab& FA, int c2t0,
+                                               f32x4 (&Yre)[MT][CT], f32x4 (&Yim)[MT][CT], int strip0 = 0,
+                                               int sstep = 1, int rot = 0) {
+  fwd_wave_split_pass<PR, MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, rot);
+  if constexpr (kRangeGuard<PR>) {
+    f32x4 fr[MT * CT], fi[MT * CT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        fr[a * CT + b] = Yre[a][b];
+        fi[a * CT + b] = Yim[a][b];
+      }
+    if (wave_any_beyond(fr, fi, 3.0e38f)) {
+      const int lane = lane_id();
+      const int r16 = lane & 15, g = lane >> 4;
+      float c = 0.f;
+      for (int strip = strip0; strip < NB; strip += sstep)
+        for (int kb = 0; kb < NB; ++kb) {
+          const int row = strip * 16 + r16, col0 = kb * 16 + 4 * g;
+          c = absmax_c4(c, combine(src, load_raw(src, row, col0)));
+        }
+      const float sc = guard_scale(wave_max(c), NB * 16);
+      if (sc > 0.f) {
+        const ScaledSrc<Src> scaled{src, sc};
+        fwd_wave_split_pass<PR, MT, CT>(scaled, NB, FA, c2t0, Yre, Yim, strip0, sstep, rot);
+        const float inv = 1.f / sc;
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+          for (int b = 0; b < CT; ++b) {
+            Yre[a][b] *= inv;
+            Yim[a][b] *= inv;
+          }
+      }
+    }
+  }
+}
+
 // Split adjoint, stage 2 (transposed) of column tile kt2 from the split
 // stage-1 operands: X^T[k2][k1] = sum_c1 S[c1][k2] conj(F[c1][k1]), two row
 // tiles at a time with ping-pong twiddle fetches; sink.put<true> receives
 // the X^T tiles.
 template <class PR, int MT, class Sink, class Tab>
 __device__ __forceinline__ void adj_stage2_split(const SplitOp<PR> (&ops)[MT], int NB, const Tab& FT, int kt2,
-                                                 Sink& sink) {
+                                                 Sink& sink, float inv = 1.f) {
   const int lane = lane_id();
   auto fetch2 = [&](int k1t, int c1t, TwS<PR>& fa, TwS<PR>& fb) {
     const int k1b = (k1t + 1 < NB) ? k1t + 1 : k1t;
@@ -297,6 +405,12 @@ __device__ __forceinline__ void adj_stage2_split(const SplitOp<PR> (&ops)[MT], i
       Xim1 = PR::mfma(o.iml, fb[cur].h, Xim1);
     }
     if constexpr ((MT & 1) != 0) fetch2(k1n, 0, fa[0], fb[0]);
+    if (inv != 1.f) {  // range-guarded input (FP16): undo its scale
+      Xre0 *= inv;
+      Xim0 *= inv;
+      Xre1 *= inv;
+      Xim1 *= inv;
+    }
     sink.template put<true>(k1t, kt2, Xre0, Xim0);
     if (two) sink.template put<true>(k1t + 1, kt2, Xre1, Xim1);
   }
@@ -353,13 +467,43 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
       stage1(f, y);
     }
   }
+  float inv = 1.f;
+  if constexpr (kRangeGuard<PR>) {
+    // S is split next: every component must fit FP16 (an inf or NaN here
+    // also reports an input component beyond it)
+    if (wave_any_beyond(Sre, Sim, kF16Max)) {
+      float c = 0.f;
+      for (int kb = 0; kb < MT; ++kb)
+        for (int c1t = 0; c1t < MT; ++c1t) c = absmax_c4(c, ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g));
+      const float sc = guard_scale(wave_max(c), MT * 16);
+      if (sc > 0.f) {
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+          Sre[a] = zero4();
+          Sim[a] = zero4();
+        }
+        for (int kb = 0; kb < MT; ++kb) {
+          const TwS<PR> f = FT.template s16<PR>((size_t)kt2 * MT + kb, lane);
+          c4 y[MT];
+#pragma unroll
+          for (int c1t = 0; c1t < MT; ++c1t) {
+            const c4 v = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) y[c1t].v[i] = make_float2(v.v[i].x * sc, v.v[i].y * sc);
+          }
+          stage1(f, y);
+        }
+        inv = 1.f / sc;
+      }
+    }
+  }
   // stage-2 operands from the accumulators: S^T rows (k2) x c1, times conj(F)
   SplitOp<PR> ops[MT];
 #pragma unroll
   for (int c1t = 0; c1t < MT; ++c1t) {
     ops[c1t] = split_c4<PR, true>(c4_of(Sre[c1t], Sim[c1t]));
   }
-  adj_stage2_split<PR, MT>(ops, NB, FT, kt2, sink);
+  adj_stage2_split<PR, MT>(ops, NB, FT, kt2, sink, inv);
 }
 
 // ---------------------------------------------------------------------------
@@ -373,10 +517,34 @@ __device__ __forceinline__ void adj_patch_split(const YSrc& ysrc, int NB, const 
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
   SplitOp<PR> ys[MT][MT];  // [column block kb][row tile c1t]
+  float cmax = 0.f;
 #pragma unroll
   for (int kb = 0; kb < MT; ++kb)
 #pragma unroll
-    for (int c1t = 0; c1t < MT; ++c1t) ys[kb][c1t] = split_c4<PR, true>(ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g));
+    for (int c1t = 0; c1t < MT; ++c1t) {
+      const c4 v = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+      if constexpr (kRangeGuard<PR>) cmax = absmax_c4(cmax, v);
+      ys[kb][c1t] = split_c4<PR, true>(v);
+    }
+  float inv = 1.f;
+  if constexpr (kRangeGuard<PR>) {
+    // every S component is bounded by 2 (MT 16) cmax: scale the coefficients
+    // down when that bound passes 2^15 (never for data of ordinary range)
+    const float sc = guard_scale(wave_max(cmax), MT * 16);
+    if (sc > 0.f && sc < 1.f) {
+#pragma unroll
+      for (int kb = 0; kb < MT; ++kb)
+#pragma unroll
+        for (int c1t = 0; c1t < MT; ++c1t) {
+          const c4 v = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
+          c4 w;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) w.v[i] = make_float2(v.v[i].x * sc, v.v[i].y * sc);
+          ys[kb][c1t] = split_c4<PR, true>(w);
+        }
+      inv = 1.f / sc;
+    }
+  }
   for (int kt2 = 0; kt2 < NB; ++kt2) {
     // stage 1: S[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2]) for this tile
     f32x4 Sre[MT], Sim[MT];
@@ -405,7 +573,7 @@ __device__ __forceinline__ void adj_patch_split(const YSrc& ysrc, int NB, const 
     SplitOp<PR> ops[MT];
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) ops[c1t] = split_c4<PR, true>(c4_of(Sre[c1t], Sim[c1t]));
-    adj_stage2_split<PR, MT>(ops, NB, FT, kt2, sink);
+    adj_stage2_split<PR, MT>(ops, NB, FT, kt2, sink, inv);
   }
 }
 

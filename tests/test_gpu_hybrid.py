@@ -73,3 +73,21 @@ def test_hybrid_at_scale_reduces_error(pk):
     print(f"rel error vs truth: init {e0:.3f} -> {e1:.3f}", flush=True)
     assert len(hist) == 15 and all(np.isfinite(h[2]) for h in hist)
     assert e1 < 0.8 * e0
+
+
+def test_split_reconstruction_error_within_one_percent_of_fp32(pk):
+    """The warm-started workload reconstructed by Algorithm 3 with its
+    partial-transform phase in each precision (10 sweeps at m = 32, then 10
+    full-window sweeps): the split precisions end within 1 % (relative) of
+    the FP32 run's error against the true object."""
+    import bench
+    import workloads
+    print("recon split vs fp32", flush=True)
+    case = workloads.pie_at_scale()
+    res = {p: bench.recon_study(torch, pk, p, iters_pft=10, iters_full=10, tol_full=0.0, case=case)
+           for p in ("fp32", "split_bf16", "split_fp16")}
+    e32 = res["fp32"]["final_error"]
+    assert res["fp32"]["final_error"] < 0.5 * res["fp32"]["initial_error"]
+    for p in ("split_bf16", "split_fp16"):
+        assert res[p]["sweeps"] == [10, 10]
+        assert abs(res[p]["final_error"] - e32) <= 0.01 * e32
