@@ -181,29 +181,62 @@ pftpie_status pft2d_adjoint(pftpie_plan plan, const void* y, void* psi,
                             int64_t batch, void* stream);
 
 /* ------------------------------------------------------------------------ */
-/* Uneven batch: many patches of different sizes in one launch.
+/* Uneven batch: many patches of different sizes in one persistent launch
+ * (the partial transform of each patch, Sec. 3.1 / Appendix A, with the
+ * per-axis window sizes left free as the paper leaves them).
  * Descriptor i: patch side n, window m, and element offsets (complex
  * elements) of its input and output inside the packed `in` / `out` arrays.
  * Forward: in holds n*n, out holds m*m elements per descriptor; adjoint the
- * reverse.  Every (n, m) pair present must be one of the plans given.
+ * reverse.  At most 8 distinct (n, m) classes; output blocks must not
+ * overlap.  Work items (column-tile groups of a patch) are ordered longest
+ * first and pulled by the waves of one persistent kernel from a device
+ * counter; every wave leaves once the counter passes the item count.
  *
- * pftpie_group_create: validates the descriptors on the host (sizes in
- *   range, blocks inside the packed arrays, outputs disjoint), orders the
- *   work longest-first and uploads it.  in_len / out_len are the lengths of
- *   the packed arrays in complex elements.  Synchronous, allocates. */
+ * Two forms share that kernel.
+ *
+ * Per call, over host descriptors and a caller workspace:
+ * pft2d_grouped_workspace_size: bytes of workspace for these descriptors
+ *   (an upper bound valid for any launch choices of the plans).
+ * pft2d_forward_grouped / pft2d_adjoint_grouped: the transforms of every
+ *   descriptor.  Each (n, m) present needs a live plan of precision `prec`
+ *   (and DFT length n) created on the current device, whose twiddle tables
+ *   are used; a missing one is PFTPIE_E_INVALID.  in / out: device
+ *   complex64 packed arrays, 16-byte aligned, disjoint; their extents are
+ *   those the descriptors reach.  workspace: device memory, 256-byte
+ *   aligned, at least pft2d_grouped_workspace_size bytes, disjoint from the
+ *   data (it receives the work list and the counter).  The descriptors are
+ *   validated and the work list built on the host, then copied to the
+ *   workspace on `stream` (the copy takes the host data before the call
+ *   returns); nothing is allocated.  A workspace must not be shared by
+ *   calls that may run at the same time.
+ *
+ * Group object, for repeated runs of one descriptor set:
+ * pftpie_group_create: validates the descriptors (sizes in range, blocks
+ *   inside the packed arrays of in_len / out_len complex elements, outputs
+ *   disjoint), uploads the work list and instantiates a hipGraph (a counter
+ *   reset node, then the persistent kernel node).  Synchronous, allocates.
+ * pft2d_group_run: replays that graph on `stream` (its buffers are updated
+ *   when in / out differ from the previous run's); allocates nothing. */
 typedef struct {
   int32_t n, m;
   int64_t in_offset, out_offset;
 } pft2d_desc;
 typedef struct pft2d_group_s* pft2d_group;
 
+pftpie_status pft2d_grouped_workspace_size(const pft2d_desc* host_desc, int64_t count, int32_t adjoint,
+                                           size_t* bytes);
+pftpie_status pft2d_forward_grouped(const pft2d_desc* host_desc, int64_t count, const void* in, void* out,
+                                    pftpie_precision prec, void* workspace, size_t ws_bytes, void* stream);
+pftpie_status pft2d_adjoint_grouped(const pft2d_desc* host_desc, int64_t count, const void* in, void* out,
+                                    pftpie_precision prec, void* workspace, size_t ws_bytes, void* stream);
+
 pftpie_status pftpie_group_create(const pftpie_plan* plans, int32_t nplans,
                                   const pft2d_desc* host_desc, int64_t count,
                                   int64_t in_len, int64_t out_len, int32_t adjoint,
                                   pft2d_group* out);
 pftpie_status pftpie_group_destroy(pft2d_group group);
-/* Run the whole uneven batch in one persistent launch (all plans must share
- * one precision).  in / out: device complex64 packed arrays. */
+/* Run the whole uneven batch (all plans share one precision).  in / out:
+ * device complex64 packed arrays. */
 pftpie_status pft2d_group_run(pft2d_group group, const void* in, void* out, void* stream);
 
 /* ------------------------------------------------------------------------ */

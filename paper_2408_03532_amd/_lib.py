@@ -58,6 +58,9 @@ SIGNATURES = {
                                   ctypes.POINTER(c_group)]),
     "pftpie_group_destroy": (i32, [c_group]),
     "pft2d_group_run": (i32, [c_group, vp, vp, vp]),
+    "pft2d_grouped_workspace_size": (i32, [ctypes.POINTER(Desc), i64, i32, ctypes.POINTER(sz)]),
+    "pft2d_forward_grouped": (i32, [ctypes.POINTER(Desc), i64, vp, vp, i32, vp, sz, vp]),
+    "pft2d_adjoint_grouped": (i32, [ctypes.POINTER(Desc), i64, vp, vp, i32, vp, sz, vp]),
     "pie_scan_create": (i32, [c_plan, ctypes.POINTER(i32), i32, i32, i32, ctypes.POINTER(c_scan)]),
     "pie_scan_destroy": (i32, [c_scan]),
     "pie_workspace_size": (i32, [c_scan, ctypes.POINTER(PieParams), ctypes.POINTER(sz)]),

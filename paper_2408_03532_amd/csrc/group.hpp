@@ -47,12 +47,12 @@ struct pft2d_group_s {
   pftpie::GroupItem* items;    // device
   unsigned long long* counter; // device
   int64_t nitems, in_len, out_len;
-  // explicitly built graph: reset node -> persistent kernel node
+  // graph built and instantiated at creation: reset node -> persistent
+  // kernel node; runs update the kernel node's buffers when they change
   hipGraph_t graph;
   hipGraphExec_t exec;
   hipGraphNode_t kernel_node;
   const void* graph_in;
   void* graph_out;
-  int use_graph;
   unsigned grid;
 };

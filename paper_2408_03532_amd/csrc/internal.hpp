@@ -57,6 +57,13 @@ struct pftpie_plan_s {
 
 namespace pftpie {
 
+// Live plans, for the per-call grouped transforms: a plan registers at
+// creation and leaves at destruction.  find_plan returns a live plan of
+// (n, m, prec) with DFT length n on `device`, or null.
+void register_plan(pftpie_plan_s* p);
+void unregister_plan(pftpie_plan_s* p);
+pftpie_plan_s* find_plan(int n, int m, pftpie_precision prec, int device);
+
 // Thread-local error message plumbing.
 pftpie_status fail(pftpie_status s, const std::string& msg);
 pftpie_status hip_fail(hipError_t e, const char* where);

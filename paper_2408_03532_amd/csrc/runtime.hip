@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,26 @@ pftpie_status fail(pftpie_status s, const std::string& msg) {
 pftpie_status hip_fail(hipError_t e, const char* where) {
   g_last_error = std::string(where) + ": " + hipGetErrorString(e);
   return PFTPIE_E_DEVICE;
+}
+
+static std::mutex g_plans_mu;
+static std::vector<pftpie_plan_s*> g_plans;
+
+void register_plan(pftpie_plan_s* p) {
+  std::lock_guard<std::mutex> lock(g_plans_mu);
+  g_plans.push_back(p);
+}
+
+void unregister_plan(pftpie_plan_s* p) {
+  std::lock_guard<std::mutex> lock(g_plans_mu);
+  g_plans.erase(std::remove(g_plans.begin(), g_plans.end(), p), g_plans.end());
+}
+
+pftpie_plan_s* find_plan(int n, int m, pftpie_precision prec, int device) {
+  std::lock_guard<std::mutex> lock(g_plans_mu);
+  for (pftpie_plan_s* p : g_plans)
+    if (p->n == n && p->m == m && p->prec == prec && p->device == device && p->period == n) return p;
+  return nullptr;
 }
 
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -190,12 +211,14 @@ pftpie_status pftpie_plan_create_period(int32_t n, int32_t m, int32_t period, pf
       return hip_fail(e, "plan_create: fast-transform twiddles");
     }
   }
+  register_plan(p);
   *out = p;
   return PFTPIE_OK;
 }
 
 pftpie_status pftpie_plan_destroy(pftpie_plan plan) {
   if (!plan) return PFTPIE_OK;
+  unregister_plan(plan);
   (void)hipFree(plan->fa);
   (void)hipFree(plan->ft);
   if (plan->fft_tw) (void)hipFree(plan->fft_tw);

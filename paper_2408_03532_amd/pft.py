@@ -221,6 +221,41 @@ class Group:
         return out
 
 
+def _descs(descs):
+    import numpy as np
+    d = np.asarray(descs, dtype=np.int64).reshape(-1, 4)
+    arr = (_lib.Desc * max(1, len(d)))()
+    for i, (n, m, io, oo) in enumerate(d):
+        arr[i] = _lib.Desc(int(n), int(m), int(io), int(oo))
+    return d, arr
+
+
+def grouped_workspace_bytes(descs, adjoint=False):
+    d, arr = _descs(descs)
+    nb = ctypes.c_size_t()
+    _lib.call("pft2d_grouped_workspace_size", arr, len(d), int(bool(adjoint)), ctypes.byref(nb))
+    return nb.value
+
+
+def pft2d_grouped(descs, inp, out, precision="fp32", adjoint=False, workspace=None):
+    """Per-call uneven batch (pft2d_forward_grouped / pft2d_adjoint_grouped):
+    descriptors (n, m, in_offset, out_offset) over packed complex64 arrays;
+    the plans of every (n, m) are created (and cached) first, since the call
+    takes the twiddle tables of live plans.  Returns out."""
+    d, arr = _descs(descs)
+    _require(inp, "inp")
+    _require(out, "out")
+    for n, m in sorted({(int(a), int(b)) for a, b in d[:, :2]}):
+        get_plan(n, m, precision, inp.device)
+    need = grouped_workspace_bytes(d, adjoint)
+    ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=inp.device)
+    name = "pft2d_adjoint_grouped" if adjoint else "pft2d_forward_grouped"
+    with torch.cuda.device(inp.device):
+        _lib.call(name, arr, len(d), ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                  _lib.PRECISION[precision], ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(inp))
+    return out
+
+
 class PolyPlan:
     """The paper's polynomial partial Fourier transform (Sec. 3.1,
     Algorithms 1-2; Appendix A, Algorithms 4-5) for n x n patches, crop m,

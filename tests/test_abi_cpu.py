@@ -115,3 +115,26 @@ def test_poly_create_rejected_on_the_host(n, m, p, eps, status, msg):
     assert L.pftpie_poly_create(n, m, p, eps, ctypes.byref(h)) == status
     assert h.value is None
     assert msg in L.pftpie_last_error()
+
+
+def test_grouped_calls_reject_bad_arguments_on_the_host():
+    L = pk.lib()
+    d = (_lib.Desc * 2)(_lib.Desc(32, 8, 0, 0), _lib.Desc(64, 16, 1024, 64))
+    nb = ctypes.c_size_t(0)
+    assert L.pft2d_grouped_workspace_size(d, 2, 0, ctypes.byref(nb)) == 0
+    assert nb.value >= 256 + (2 + 1) * 24
+    assert L.pft2d_grouped_workspace_size(d, 2, 1, ctypes.byref(nb)) == 0
+    assert L.pft2d_grouped_workspace_size(d, 2, 0, None) == 1
+    assert L.pft2d_grouped_workspace_size(None, 2, 0, ctypes.byref(nb)) == 1
+    bad = (_lib.Desc * 1)(_lib.Desc(8, 9, 0, 0))
+    assert L.pft2d_grouped_workspace_size(bad, 1, 0, ctypes.byref(nb)) == 1
+    p = ctypes.c_void_p(1 << 20)
+    for args, msg in [((d, -1, p, p, 0, p, 1 << 20, None), b"count < 0"),
+                      ((None, 2, p, p, 0, p, 1 << 20, None), b"NULL"),
+                      ((d, 2, p, p, 9, p, 1 << 20, None), b"unknown precision"),
+                      ((d, 2, None, p, 0, p, 1 << 20, None), b"NULL data pointer"),
+                      ((d, 2, ctypes.c_void_p((1 << 20) + 8), p, 0, p, 1 << 20, None), b"16-byte aligned"),
+                      ((d, 2, p, p, 0, ctypes.c_void_p((1 << 20) + 64), 1 << 20, None), b"256-byte aligned")]:
+        assert L.pft2d_forward_grouped(*args) == 1
+        assert msg in L.pftpie_last_error()
+    assert L.pft2d_adjoint_grouped(d, 0, None, None, 0, None, 0, None) == 0   # nothing to do

@@ -58,23 +58,79 @@ def test_small_mixed_forward_and_adjoint(pk, prec):
     assert rel(xa, refa) <= TOLS[prec]
 
 
-def test_graph_replay_with_new_buffers_and_without_graph(pk, monkeypatch):
+def test_graph_replay_with_new_buffers_and_the_per_call_form(pk):
+    """The group's graph replayed on alternating buffers (its kernel node is
+    updated, never rebuilt), with the program's own work and
+    synchronisations between replays; every replay equals the per-call
+    grouped transform (same kernel, no graph) bit for bit."""
     d, tin, tout = mixed_descs(SMALL, seed=3)
     x1 = workloads.grouped_inputs(d, tin, seed=1)
     x2 = workloads.grouped_inputs(d, tin, seed=2)
     g = pk.Group(d, tin, tout)
     a = torch.from_numpy(x1).cuda()
     b = torch.from_numpy(x2).cuda()
-    outs = [g.run(a), g.run(b), g.run(a)]
+    outs = []
+    for k in range(6):
+        outs.append(g.run(a if k % 2 == 0 else b))
+        (a * 2).sum().item()          # eager work and a host sync between replays
     torch.cuda.synchronize()
     r1 = opft.grouped_forward(d, x1, tout)
     r2 = opft.grouped_forward(d, x2, tout)
     assert rel(outs[0].cpu().numpy(), r1) <= 1e-5
     assert rel(outs[1].cpu().numpy(), r2) <= 1e-5
-    assert torch.equal(outs[0], outs[2])
-    monkeypatch.setenv("PFTPIE_GROUP_GRAPH", "0")
-    g2 = pk.Group(d, tin, tout)
-    assert torch.equal(g2.run(a), outs[0])
+    for k in range(2, 6):
+        assert torch.equal(outs[k], outs[k % 2])
+    direct = torch.zeros(tout, dtype=torch.complex64, device="cuda")
+    pk.pft2d_grouped(d, a, direct)
+    assert torch.equal(direct, outs[0])
+
+
+@pytest.mark.parametrize("prec", sorted(TOLS))
+def test_per_call_grouped_forward_and_adjoint(pk, prec):
+    """pft2d_forward_grouped / pft2d_adjoint_grouped over host descriptors
+    and a caller workspace, against the oracle; a second call with fewer
+    descriptors reuses the workspace."""
+    print("grouped per call", prec, flush=True)
+    d, tin, tout = mixed_descs(SMALL, seed=5, pad=2)
+    x = workloads.grouped_inputs(d, tin, seed=17)
+    ws = torch.empty(pk.grouped_workspace_bytes(d), dtype=torch.uint8, device="cuda")
+    y = torch.zeros(tout, dtype=torch.complex64, device="cuda")
+    pk.pft2d_grouped(d, torch.from_numpy(x).cuda(), y, prec, workspace=ws)
+    assert rel(y.cpu().numpy(), opft.grouped_forward(d, x, tout)) <= TOLS[prec]
+    sub = d[:7]
+    y2 = torch.zeros(tout, dtype=torch.complex64, device="cuda")
+    pk.pft2d_grouped(sub, torch.from_numpy(x).cuda(), y2, prec, workspace=ws)
+    ref2 = opft.grouped_forward(sub, x, tout)
+    assert rel(y2.cpu().numpy(), ref2) <= TOLS[prec]
+    da = workloads.adjoint_descs(d)
+    ya = workloads.grouped_inputs(da, tout, seed=18, adjoint=True)
+    xa = torch.zeros(tin, dtype=torch.complex64, device="cuda")
+    pk.pft2d_grouped(da, torch.from_numpy(ya).cuda(), xa, prec, adjoint=True)
+    assert rel(xa.cpu().numpy(), opft.grouped_adjoint(da, ya, tin)) <= TOLS[prec]
+
+
+def test_per_call_grouped_rejects_bad_calls(pk):
+    from paper_2408_03532_amd import _lib
+    d = np.array([(32, 8, 0, 0), (64, 16, 1024, 64)], dtype=np.int64)
+    x = torch.zeros(1024 + 4096, dtype=torch.complex64, device="cuda")
+    y = torch.zeros(64 + 256, dtype=torch.complex64, device="cuda")
+    pk.pft2d_grouped(d, x, y)                            # creates the plans
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pk.PftpieError, match="workspace"):
+        pk.pft2d_grouped(d, x, y, workspace=small)
+    with pytest.raises(pk.PftpieError, match="overlap"):
+        pk.pft2d_grouped(np.array([(32, 8, 0, 0), (32, 8, 1024, 32)]), x, y)
+    with pytest.raises(pk.PftpieError, match="overlap"):
+        pk.pft2d_grouped(d, x, x[8:])
+    arr = (_lib.Desc * 1)(_lib.Desc(48, 12, 0, 0))       # no live plan of (48, 12)
+    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    st = _lib.lib().pft2d_forward_grouped(arr, 1, ctypes_ptr(x), ctypes_ptr(y), 0, ctypes_ptr(ws), 4096, None)
+    assert st == 1 and b"no live plan" in _lib.lib().pftpie_last_error()
+
+
+def ctypes_ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
 
 
 @pytest.mark.parametrize("prec", sorted(TOLS))
