@@ -1,6 +1,7 @@
 """Benchmark of the batched partial transform and the PIE sweep on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+    python bench.py --workload {pft,group,pie,loss,peaks} [--precision P] [--steps K]
 
 Headline workload: the standalone batched transform, 4096 complex64 patches
 of 256 x 256 (Re/Im iid N(0,1), seeded), keeping the centred m = 64
@@ -9,18 +10,23 @@ pft2d_adjoint over an independent [4096][64][64] batch (inputs resident in
 HBM before timing starts).  value = patches per second (one forward and one
 adjoint per patch).
 
-The roofline object describes the forward kernel: achieved = its
-algorithmic flops per launch (8 n m (n + m) per patch, four real products
-per complex multiply-add) over its average duration, timed with events on
-the stream the kernel runs on.  The FP32 kernel forms each complex product
-from three real MFMA products (Gauss), so it issues 6 n m (n + m) flops per
-patch and frac can exceed 1; mfma_issued_frac is the issued work over the
-peak.  The
+The roofline object describes the forward kernel, timed with events on the
+stream it runs on.  FP32: the contraction forms each complex product from
+three real matrix products (Gauss), so its algorithmic work is
+6 n m (n + m) real flops per patch, the bound is the FP32 matrix rate, and
+achieved / frac use that count; the conventional 8 n m (n + m) rate is
+reported beside it (alg8_*).  Split precisions: HBM-bound; achieved is the
+compulsory bytes (n^2 + m^2) x 8 per patch over the duration.  Fractions are
+given against the published peaks and against the peaks measured in the
+same run (a 1 GiB device copy; matrix-core loops on random operands).  The
 cpu_baseline leg times the FP64 oracle on a bounded sample of the same
-patches on the host cores and reports the GPU outputs' relative error
-against it.  The "extra" object holds the secondary measurements: the split
-precisions on the same batch, PIE iterations per second on the at-scale and
-tiny workloads, and the uneven grouped batch.
+patches on the host cores, with all BLAS threads and with one, and reports
+the GPU outputs' relative error against it.  "extra" holds the secondary
+measurements: the split precisions on the same batch, torch.fft.fft2 + crop
+as a context comparator, PIE iterations per second on the at-scale and tiny
+workloads, the reconstruction study, the uneven batch and the loss.
+
+--workload runs one workload's kernels only (for counter collection).
 
 Prints one JSON line.
 """
@@ -39,13 +45,15 @@ METRIC = "PFT patches/sec + PIE iters/sec at stated rel. error vs FP64 oracle"
 PEAK_FP32 = 157.3      # TFLOP/s, dense FP32 (vector and matrix)
 PEAK_HBM = 8000.0      # GB/s
 PEAK_BF16 = 2516.6     # TFLOP/s, dense BF16 / FP16 MFMA
+CPU_SAMPLE = 256       # patches of the batch the oracle runs on
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pft2d_forward_4096x256_m64_hbm_traffic.md")
 # sources that define the forward kernel; the recorded traffic is reported
 # only while they are unchanged since the counters were taken
-FORWARD_SOURCES = ["device_common.hpp", "pft_engine.hpp", "pft_split.hpp", "kernels_pft.hip", "internal.hpp",
+FORWARD_SOURCES = ["device_common.hpp", "pft_engine.hpp", "pft_split.hpp", "pft_kernels.hpp", "kernels_pft.hip",
+                   "kernels_pft_f32.hip", "kernels_pft_bf16.hip", "kernels_pft_f16.hip", "internal.hpp",
                    "twiddle.cpp", "twiddle.hpp"]
 
 
@@ -83,6 +91,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--workload", default=None, choices=["pft", "group", "pie", "loss", "peaks"],
+                    help="run only this workload's kernels (profiling)")
     return ap.parse_args()
 
 
@@ -115,10 +125,12 @@ def make_inputs(torch, n, m, B):
 
 
 def cpu_baseline(n, m, gpu_out, seconds):
-    """FP64 oracle timed on the host: forward + adjoint per patch, over
-    patches of the same seeded batch, until `seconds` have elapsed.  Also
+    """FP64 oracle timed on the host: forward + adjoint per patch, cycling
+    over the first CPU_SAMPLE patches of the same seeded batch, until
+    `seconds` have elapsed (then for half as long on one BLAS thread).  Also
     returns the relative error of each GPU result given in gpu_out
-    ({name: (forward[:64], adjoint[:64])}) against the oracle."""
+    ({name: (forward[:CPU_SAMPLE], adjoint[:CPU_SAMPLE])}) against the
+    oracle."""
     import workloads
     from oracle import pft as opft
     try:
@@ -126,18 +138,19 @@ def cpu_baseline(n, m, gpu_out, seconds):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
-    idx = np.arange(64)
+    S = CPU_SAMPLE
+    idx = np.arange(S)
     xs = workloads.pft_patches(n, idx)
     ys = workloads.pft_coeffs(m, idx)
-    fwd_ref = np.zeros((64, m, m), complex)
-    adj_ref = np.zeros((64, n, n), complex)
+    fwd_ref = np.zeros((S, m, m), complex)
+    adj_ref = np.zeros((S, n, n), complex)
     done = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds or done < 64:
-        k = done % 64
+    while time.perf_counter() - t0 < seconds or done < S:
+        k = done % S
         f = opft.forward(xs[k], m)
         a = opft.adjoint(ys[k], n)
-        if done < 64:
+        if done < S:
             fwd_ref[k], adj_ref[k] = f, a
         done += 1
     el = time.perf_counter() - t0
@@ -145,10 +158,23 @@ def cpu_baseline(n, m, gpu_out, seconds):
     for name, (gf, ga) in gpu_out.items():
         errs[name] = {"forward": float(np.linalg.norm(gf - fwd_ref) / np.linalg.norm(fwd_ref)),
                       "adjoint": float(np.linalg.norm(ga - adj_ref) / np.linalg.norm(adj_ref)),
-                      "patches_checked": 64}
+                      "patches_checked": S}
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            k1, t1 = 0, time.perf_counter()
+            while time.perf_counter() - t1 < seconds / 2:
+                opft.forward(xs[k1 % S], m)
+                opft.adjoint(ys[k1 % S], n)
+                k1 += 1
+            one = {"value": k1 / (time.perf_counter() - t1), "cores": 1}
+    except Exception:
+        pass
     return ({"value": done / el, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
-             "sample": f"{done} forward+adjoint patch pairs (n={n}, m={m}, the first 64 patches of the "
-                       f"batch, cycled) in {el:.1f} s, numpy complex128"}, errs)
+             "sample": f"{done} forward+adjoint patch pairs (n={n}, m={m}, the first {S} patches of the "
+                       f"batch, cycled) in {el:.1f} s, numpy complex128",
+             "one_thread": one}, errs)
 
 
 def pie_at_scale_rate(torch, pk, precision, sweeps=10, warmup=2, m=32, method="auto"):
@@ -261,6 +287,38 @@ def loss_rate(torch, pk, precision="fp32", steps=5, warmup=1):
             "fwd_bwd_tflops_alg": 2 * flops / ((f + b) * 1e-3) / 1e12, "precision": precision}
 
 
+def measured_peaks(torch, pk):
+    """Device copy rate of 1 GiB (read + write bytes over time) and the
+    matrix-core rates of the library's MFMA loops, measured now."""
+    import ctypes
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = time_calls(torch, lambda: dst.copy_(src), 10, 3)
+    out = {"copy_gbs": 2 * src.numel() * 8 / (ms * 1e-3) / 1e9}
+    del src, dst
+    v = [ctypes.c_double() for _ in range(3)]
+    pk.lib().pftpie_measure_mfma_peaks(*[ctypes.byref(x) for x in v])
+    out.update({"fp32_tflops": v[0].value, "bf16_tflops": v[1].value, "fp16_tflops": v[2].value})
+    return out
+
+
+def fft_crop_rate(torch, x, m, y_ref, steps=5, warmup=2):
+    """Context comparator: torch.fft.fft2 of the whole batch, then the centred
+    m x m window (frequencies -m/2 .. m/2 - 1 per axis), on the same GPU."""
+    n = x.shape[-1]
+    idx = (torch.arange(m, device=x.device) - m // 2) % n
+    out = {}
+
+    def run():
+        out["y"] = torch.fft.fft2(x)[:, idx][:, :, idx]
+    ms = time_calls(torch, run, steps, warmup)
+    y = out.pop("y")
+    d = float(torch.linalg.vector_norm(y[:64] - y_ref[:64]) / torch.linalg.vector_norm(y_ref[:64]))
+    del y
+    return {"ms": ms, "patches_per_s": x.shape[0] / (ms * 1e-3), "rel_diff_vs_pft2d_forward": d,
+            "note": "context only: full transform then crop (rocFFT through torch), not a product path"}
+
+
 ERR_LEVELS = (0.5, 0.3, 0.2, 0.15, 0.1, 0.07, 0.05, 0.03, 0.02)
 
 
@@ -363,6 +421,43 @@ def group_rate(torch, pk, precisions, steps=5, warmup=2):
     return out
 
 
+def workload_only(torch, pk, args):
+    """One workload's kernels, a few runs each (for counter collection)."""
+    import workloads
+    prec = args.precision
+    out = {"workload": args.workload, "precision": prec}
+    if args.workload == "peaks":
+        out.update(measured_peaks(torch, pk))
+    elif args.workload == "pft":
+        n, m, B = 256, 64, args.batch
+        x, yin = make_inputs(torch, n, m, B)
+        yout = torch.empty(B, m, m, dtype=torch.complex64, device="cuda")
+        xout = torch.empty(B, n, n, dtype=torch.complex64, device="cuda")
+        pl = pk.get_plan(n, m, prec)
+        out["forward_ms"] = time_calls(torch, lambda: pl.forward(x, yout), args.steps, 1)
+        out["adjoint_ms"] = time_calls(torch, lambda: pl.adjoint(yin, xout), args.steps, 1)
+    elif args.workload == "group":
+        out.update(group_rate(torch, pk, [prec], steps=args.steps, warmup=1)[prec])
+    elif args.workload == "pie":
+        out.update(pie_at_scale_rate(torch, pk, prec, sweeps=args.steps, warmup=1))
+    elif args.workload == "loss":
+        out.update(loss_rate(torch, pk, prec, steps=args.steps, warmup=1))
+    if args.copy_calibration:
+        copy_calibration(torch, out)
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibration(torch, out):
+    """A plain 1 GiB device-to-device copy (2 GiB of HBM traffic) whose
+    counters scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = 2 * src.numel() * 8
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -372,6 +467,10 @@ def main():
         sys.exit(2)
     import torch
     import paper_2408_03532_amd as pk
+
+    if args.workload:
+        workload_only(torch, pk, args)
+        return
 
     n, m, B = 256, 64, args.batch
     prec = args.precision
@@ -398,18 +497,31 @@ def main():
     el = time.perf_counter() - t0
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
     adj_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
-    gpu_out = {prec: (yout[:64].cpu().numpy(), xout[:64].cpu().numpy())}
+    S = CPU_SAMPLE
+    gpu_out = {prec: (yout[:S].cpu().numpy(), xout[:S].cpu().numpy())}
 
-    flops = 8.0 * n * m * (n + m) * B
+    peaks = measured_peaks(torch, pk)
+    alg8 = 8.0 * n * m * (n + m) * B           # 8 real flops per complex multiply-add
     bytes_fwd = (n * n + m * m) * 8.0 * B
     if prec == "fp32":
-        roof = {"bound": "mfma", "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": PEAK_FP32,
-                "unit": "TFLOP/s", "mfma_issued_flops_per_launch": 0.75 * flops,
-                "mfma_issued_frac": 0.75 * flops / (fwd_ms * 1e-3) / 1e12 / PEAK_FP32}
+        # three real matrix products per complex product: 6 real flops per
+        # complex multiply-add is the work the matrix cores must do
+        work = 6.0 * n * m * (n + m) * B
+        ach = work / (fwd_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
+                "traffic": recorded_traffic(prec), "kernel": "pft2d_forward",
+                "alg_flops_per_launch": work,
+                "alg_flops_note": "6 n m (n + m) per patch: each complex product is three real MFMA products",
+                "measured_peak": peaks["fp32_tflops"], "frac_measured": ach / peaks["fp32_tflops"],
+                "alg8_flops_per_launch": alg8, "alg8_tflops": alg8 / (fwd_ms * 1e-3) / 1e12,
+                "alg8_frac": alg8 / (fwd_ms * 1e-3) / 1e12 / PEAK_FP32}
     else:
-        roof = {"bound": "hbm", "achieved": bytes_fwd / (fwd_ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
-    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": recorded_traffic(prec), "kernel": "pft2d_forward",
-                 "alg_flops_per_launch": flops, "alg_bytes_per_launch": bytes_fwd, "kernel_ms": fwd_ms})
+        ach = bytes_fwd / (fwd_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                "traffic": recorded_traffic(prec), "kernel": "pft2d_forward", "alg_bytes_per_launch": bytes_fwd,
+                "measured_peak": peaks["copy_gbs"], "frac_measured": ach / peaks["copy_gbs"],
+                "alg8_tflops": alg8 / (fwd_ms * 1e-3) / 1e12}
+    roof.update({"kernel_ms": fwd_ms, "alg_bytes_per_launch": bytes_fwd})
     out = {
         "metric": METRIC,
         "value": B * args.steps / el,
@@ -428,8 +540,9 @@ def main():
                    "batch": B, "n": n, "m": m, "precision": prec},
         "forward_source": forward_source_hash(),
         "kernels_ms": {"forward": fwd_ms, "adjoint": adj_ms,
-                       "adjoint_tflops_alg": flops / (adj_ms * 1e-3) / 1e12},
+                       "adjoint_alg8_tflops": alg8 / (adj_ms * 1e-3) / 1e12},
         "roofline": roof,
+        "measured_peaks": peaks,
     }
 
     if not args.no_extra:
@@ -442,12 +555,17 @@ def main():
             a = time_calls(torch, lambda: pl.adjoint(yin, xout), 10, 2)
             extra[f"pft_{p}"] = {"forward_ms": f, "adjoint_ms": a, "patches_per_s": B / (f + a) * 1e3,
                                  "forward_hbm_frac": bytes_fwd / (f * 1e-3) / 1e9 / PEAK_HBM,
-                                 "forward_tflops_alg": flops / (f * 1e-3) / 1e12}
-            gpu_out[p] = (yout[:64].cpu().numpy(), xout[:64].cpu().numpy())
-        del x, xout
+                                 "forward_hbm_frac_measured": bytes_fwd / (f * 1e-3) / 1e9 / peaks["copy_gbs"],
+                                 "adjoint_hbm_frac": bytes_fwd / (a * 1e-3) / 1e9 / PEAK_HBM,
+                                 "forward_alg8_tflops": alg8 / (f * 1e-3) / 1e12}
+            gpu_out[p] = (yout[:S].cpu().numpy(), xout[:S].cpu().numpy())
+        yref = pk.get_plan(n, m, "fp32").forward(x)
+        extra["torch_fft2_crop"] = fft_crop_rate(torch, x, m, yref)
+        del x, xout, yref
         torch.cuda.empty_cache()
         extra["pie_at_scale_phase1"] = pie_at_scale_rate(torch, pk, "fp32")
         extra["pie_at_scale_phase1_split_bf16"] = pie_at_scale_rate(torch, pk, "split_bf16")
+        extra["pie_at_scale_phase1_split_fp16"] = pie_at_scale_rate(torch, pk, "split_fp16")
         extra["pie_at_scale_phase2_fft"] = pie_at_scale_rate(torch, pk, "fp32", m=128)
         extra["pie_at_scale_phase2_dense"] = pie_at_scale_rate(torch, pk, "fp32", m=128, method="dense")
         extra["pie_masked_field_16384"] = masked_field_rate(torch, pk)
@@ -458,6 +576,7 @@ def main():
         extra["pie_tiny_batched"] = pie_tiny_rate(torch, pk, 64, 1)
         extra["group_uneven_8192"] = group_rate(torch, pk, ["fp32", "split_bf16", "split_fp16"])
         extra["amp_loss_1024x256"] = loss_rate(torch, pk)
+        extra["amp_loss_1024x256_split_bf16"] = loss_rate(torch, pk, "split_bf16")
         import workloads
         c3 = workloads.pie_at_scale()
         study = {f"hybrid_{p}": recon_study(torch, pk, p, case=c3) for p in ("fp32", "split_bf16", "split_fp16")}
@@ -466,12 +585,7 @@ def main():
         out["extra"] = extra
 
     if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = 2 * src.numel() * 8
+        copy_calibration(torch, out)
 
     if not args.no_cpu:
         out["cpu_baseline"], out["rel_err_vs_oracle"] = cpu_baseline(n, m, gpu_out, args.cpu_seconds)

@@ -349,6 +349,16 @@ pftpie_status amp_loss_backward(pie_scan scan, const void* object, const void* p
                                 void* grad_object, void* grad_probe,
                                 void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement aid (not part of the method): the matrix-core rate the device
+ * delivers, in TFLOP/s, from a loop of independent MFMA products on random
+ * register operands over 8 waves per SIMD (v_mfma_f32_16x16x4_f32 for
+ * FP32, v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation), so that
+ * roofline fractions can be given against measured as well as published
+ * peaks.  Synchronous; allocates and frees a small output buffer; runs on
+ * the current device. */
+pftpie_status pftpie_measure_mfma_peaks(double* fp32_tflops, double* bf16_tflops, double* fp16_tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,11 @@
+// PIE sweep, dense contraction in F16: the per-chunk forward / projection
+// and adjoint / update kernels of this precision.
+#include "pie_dense.hpp"
+
+namespace pftpie {
+
+void pie_chunk_dense_f16(const PieArgs& a, int c0, int cnt, hipStream_t st) { chunk_dense<PrecF16>(a, c0, cnt, st); }
+
+int pie_fwd_split_blocks_f16(int mt, bool rs) { return fwd_split_blocks_mt<PrecF16>(mt, rs); }
+
+}  // namespace pftpie

@@ -135,6 +135,16 @@ hipError_t launch_pie_fft_chunk(const PieArgs& a, int c0, int cnt, hipStream_t s
 int pie_probe_blocks(int n);
 
 #ifdef __HIPCC__
+// Position of entry q of the chunk starting at c0.  An order entry outside
+// [0, J) is clamped for addressing and reported through `valid` so that the
+// kernels contribute nothing for it.
+__device__ __forceinline__ int pos_index(const int32_t* __restrict__ order, int J, int c0, int q, bool* valid) {
+  int j = order ? order[c0 + q] : c0 + q;
+  const bool ok = (j >= 0 && j < J);
+  if (valid) *valid = ok;
+  return ok ? j : 0;
+}
+
 // psi[k1][k2] = P[k1][k2] * O[r + k1][c + k2]; zero outside the n x n patch.
 // The engines prefetch the raw probe and object values (load_raw) and form
 // the products (combine) just before the block's MFMA products.

@@ -149,3 +149,16 @@ def test_standalone_batch_full_size_sampled(pkg, prec):
     ys = workloads.pft_coeffs(m, idx)
     assert rel(xa[idx].cpu().numpy(), opft.adjoint(ys, n)) <= TOL
     assert torch.isfinite(torch.view_as_real(y)).all() and torch.isfinite(torch.view_as_real(xa)).all()
+
+
+def test_measured_peaks_are_plausible(pkg):
+    """The matrix-core loops of the measurement aid report rates within a
+    factor of the published dense peaks (FP32 157.3, BF16 / FP16 2516.6
+    TFLOP/s) and above what the transforms reach."""
+    import ctypes
+    v = [ctypes.c_double() for _ in range(3)]
+    assert pkg.lib().pftpie_measure_mfma_peaks(*[ctypes.byref(x) for x in v]) == 0
+    fp32, bf16, fp16 = (x.value for x in v)
+    print("measured peaks", fp32, bf16, fp16, flush=True)
+    assert 60.0 < fp32 < 200.0
+    assert 800.0 < bf16 < 3200.0 and 800.0 < fp16 < 3200.0
