@@ -33,6 +33,15 @@ void pie_chunk_dense_f16(const PieArgs& a, int c0, int cnt, hipStream_t st);
 int pie_fwd_split_blocks_f32(int mt, bool rs);
 int pie_fwd_split_blocks_bf16(int mt, bool rs);
 int pie_fwd_split_blocks_f16(int mt, bool rs);
+// the whole sequential sweep in one workgroup (kernels_pie_{f32,bf16,f16}.hip)
+void pie_sequential_dense_f32(const PieArgs& a, hipStream_t st);
+void pie_sequential_dense_bf16(const PieArgs& a, hipStream_t st);
+void pie_sequential_dense_f16(const PieArgs& a, hipStream_t st);
+// ... with the box, probe, residual and tables in LDS and the statistics in
+// the same launch; false when they do not fit
+bool pie_sequential_lds_f32(const PieArgs& a, hipStream_t st);
+bool pie_sequential_lds_bf16(const PieArgs& a, hipStream_t st);
+bool pie_sequential_lds_f16(const PieArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // gathers of a chunk's corrections
@@ -354,6 +363,17 @@ hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipS
 
 hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   const size_t obj = (size_t)a.H * a.W;
+  if (batch == 1 && !a.fft_tw && a.nb <= kSeqMaxNb && a.mt <= 2) {
+    // sequential sweep of small windows held in LDS: one launch per sweep
+    bool done;
+    if (a.prec == PFTPIE_SPLIT_BF16)
+      done = pie_sequential_lds_bf16(a, st);
+    else if (a.prec == PFTPIE_SPLIT_FP16)
+      done = pie_sequential_lds_f16(a, st);
+    else
+      done = pie_sequential_lds_f32(a, st);
+    if (done) return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_pie_begin, dim3(ew_blocks(obj)), dim3(256), 0, st, a);
   if (a.order) hipLaunchKernelGGL(k_pie_rank, dim3(ew_blocks((size_t)a.J)), dim3(256), 0, st, a);
   const int ntiles = a.tiles_x * a.tiles_y;
@@ -369,6 +389,18 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
       pie_chunk_dense_f32(ca, c0, cnt, st);
     return hipSuccess;
   };
+  if (batch == 1 && !a.fft_tw && a.nb <= kSeqMaxNb && a.mt <= 2) {
+    // sequential sweep of small windows: one persistent workgroup
+    if (a.prec == PFTPIE_SPLIT_BF16)
+      pie_sequential_dense_bf16(a, st);
+    else if (a.prec == PFTPIE_SPLIT_FP16)
+      pie_sequential_dense_f16(a, st);
+    else
+      pie_sequential_dense_f32(a, st);
+    hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks);
+    return hipGetLastError();
+  }
   // eq. (6) as printed (single positions): the object step, then a second
   // transform pair at the updated object for the probe step
   PieArgs obj_pass = a, probe_pass = a;

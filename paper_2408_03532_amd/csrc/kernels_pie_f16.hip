@@ -8,4 +8,10 @@ void pie_chunk_dense_f16(const PieArgs& a, int c0, int cnt, hipStream_t st) { ch
 
 int pie_fwd_split_blocks_f16(int mt, bool rs) { return fwd_split_blocks_mt<PrecF16>(mt, rs); }
 
+void pie_sequential_dense_f16(const PieArgs& a, hipStream_t st) { sequential_dense<PrecF16>(a, st); }
+
+bool pie_sequential_lds_f16(const PieArgs& a, hipStream_t st) {
+  return sequential_lds_dense<PrecF16>(a, a.fa_bytes, a.ft_bytes, st);
+}
+
 }  // namespace pftpie

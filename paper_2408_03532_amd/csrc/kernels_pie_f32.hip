@@ -8,4 +8,10 @@ void pie_chunk_dense_f32(const PieArgs& a, int c0, int cnt, hipStream_t st) { ch
 
 int pie_fwd_split_blocks_f32(int mt, bool rs) { return fwd_split_blocks_mt<PrecF32>(mt, rs); }
 
+void pie_sequential_dense_f32(const PieArgs& a, hipStream_t st) { sequential_dense<PrecF32>(a, st); }
+
+bool pie_sequential_lds_f32(const PieArgs& a, hipStream_t st) {
+  return sequential_lds_dense<PrecF32>(a, a.fa_bytes, a.ft_bytes, st);
+}
+
 }  // namespace pftpie

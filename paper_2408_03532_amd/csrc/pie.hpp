@@ -29,6 +29,7 @@ struct PieArgs {
   const void* fa;
   const void* ft;
   const float2* fft_tw;  // full-window fast transform twiddles (null: dense contraction)
+  size_t fa_bytes, ft_bytes;  // bytes of the twiddle tables
   int prec;
   int period;       // DFT length: n, or the masked field's size
   float inv_n2;     // 1 / period^2 (inverse DFT of the band change)
@@ -63,7 +64,14 @@ struct PieArgs {
 };
 
 constexpr int kStatBlocks = 2048;
-constexpr int32_t kRankAbsent = 0x7fffffff;  // rank of a position the sweep order leaves out
+constexpr int32_t kRankAbsent = 0x7fffffff;
+// Sequential sweeps (chunks of one position) of windows up to kSeqMaxNb
+// tiles of 16 per axis and up to 32 kept coefficients run in one
+// persistent workgroup.
+constexpr int kSeqMaxNb = 4;
+// LDS a sequential sweep may hold (object box, probe, residual, tables).
+constexpr size_t kSeqLdsBytes = 144 * 1024;
+constexpr size_t kSeqLdsMaxObject = 1 << 16;  // object pixels  // rank of a position the sweep order leaves out
 
 // Forward work split of the dense sweep for MT = ceil(m/16) tiles per axis:
 // CT column tiles per wave, WC column groups, WR row groups per workgroup.

@@ -57,6 +57,25 @@ __device__ __forceinline__ double pie_project_one(const PieArgs& a, int q, int j
   return valid ? d * d : 0.0;
 }
 
+// The projection of pie_project_one with the amplitude already loaded.
+__device__ __forceinline__ double pie_project_amp(const PieArgs& a, int q, bool valid, int c1, int c2, float ur,
+                                                  float ui, float av) {
+  const int m = a.m;
+  const float mag = sqrtf(ur * ur + ui * ui);
+  float2 r;
+  if (!valid) {
+    r = make_float2(0.f, 0.f);
+  } else if (mag > 0.f) {
+    const float s = av / mag - 1.f;
+    r = make_float2(s * ur, s * ui);
+  } else {
+    r = make_float2(av - ur, -ui);  // theta(0) = 0
+  }
+  a.R[(size_t)q * m * m + (size_t)c1 * m + c2] = r;
+  const double d = (double)mag - (double)av;
+  return valid ? d * d : 0.0;
+}
+
 // Forward + projection.  Block = WR x WC waves: wave (wr, wc) runs strips
 // g, g + G, ... (row group g = split * WR + wr, G = WR * splits) for
 // column-tile group wc; partial spectra of wr > 0 are added to wr = 0
@@ -393,6 +412,347 @@ static void chunk_prec(const PieArgs& a, int c0, int cnt, hipStream_t st) {
   }
 }
 
+// Sequential sweep (chunks of one position, eq. (5)) for small windows in
+// one persistent workgroup of kSeqWaves waves: for each position of the
+// order in turn, the forward (its row groups over waves, partial spectra
+// summed through LDS) and projection, a barrier, the adjoint column tiles
+// over all waves updating O (and P) in place, a barrier.  One workgroup runs
+// on one compute unit, so the barriers alone order each position's reads
+// after the previous position's writes; the launch replaces two launches
+// per position.  Literal probe steps (eq. (6) as printed) run their second
+// pass at the updated object inside the same loop.
+constexpr int kSeqWaves = 4;
+
+template <class PR, int MT, bool EXACT>
+__global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential(PieArgs a) {
+  constexpr int CT = (MT <= 2) ? MT : 2;
+  constexpr int WC = (MT + CT - 1) / CT;
+  constexpr int WR = pie_wr<MT>();
+  static_assert(WR * WC <= kSeqWaves, "the forward's waves must fit the workgroup");
+  __shared__ f32x4 part[(WR > 1 ? (WR - 1) * WC : 1) * MT * CT * 2 * 64];
+  const int w = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int wc = w % WC, wr = w / WC;
+  const bool fwd_wave = w < WR * WC;
+  const TabG FA{static_cast<const char*>(a.fa)};
+  const TabG FT{static_cast<const char*>(a.ft)};
+  const int passes = a.probe_literal ? 2 : 1;
+  for (int t = 0; t < a.J; ++t) {
+    bool valid;
+    const int j = pos_index(a.order, a.J, t, 0, &valid);
+    const int2 ps = a.pos[j];
+    for (int pass = 0; pass < passes; ++pass) {
+      PieArgs b = a;
+      if (a.probe_literal) {
+        b.probe_step = pass;  // object pass first, then the probe pass
+        b.probe_pass = pass;
+      }
+      const bool track = b.norm || b.probe_step;
+      // forward: Y of this wave's column-tile group over its row group
+      f32x4 Yre[MT][CT], Yim[MT][CT];
+      if (fwd_wave) {
+        if (track) {
+          GatherTrackSrc<EXACT> src{{b.O, b.P, b.W, b.n, ps.x, ps.y}, 0.f, 0.f};
+          fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
+          if (wc == 0) {
+            const float mp = wave_max(src.mp), mo = wave_max(src.mo);
+            if (lane == 0 && valid) {
+              atomicMax(&b.winmax[2 * j], __float_as_uint(mp));
+              atomicMax(&b.winmax[2 * j + 1], __float_as_uint(mo));
+            }
+          }
+        } else {
+          GatherSrc<EXACT> src{b.O, b.P, b.W, b.n, ps.x, ps.y};
+          fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
+        }
+        if (WR > 1 && wr > 0) {
+          f32x4* dst = part + ((size_t)((wr - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+          for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+            for (int b1 = 0; b1 < CT; ++b1) {
+              dst[((a1 * CT + b1) * 2 + 0) * 64 + lane] = Yre[a1][b1];
+              dst[((a1 * CT + b1) * 2 + 1) * 64 + lane] = Yim[a1][b1];
+            }
+        }
+      }
+      __syncthreads();
+      if (fwd_wave && wr == 0) {
+#pragma unroll
+        for (int r = 1; r < WR; ++r) {
+          const f32x4* src = part + ((size_t)((r - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+          for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+            for (int b1 = 0; b1 < CT; ++b1) {
+              Yre[a1][b1] += src[((a1 * CT + b1) * 2 + 0) * 64 + lane];
+              Yim[a1][b1] += src[((a1 * CT + b1) * 2 + 1) * 64 + lane];
+            }
+        }
+        double phi = 0.0;
+#pragma unroll
+        for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
+              if (rc.x < b.m && rc.y < b.m)
+                phi += pie_project_one(b, 0, j, valid, rc.x, rc.y, Yre[c1t][ct][i], Yim[c1t][ct][i]);
+            }
+        phi = wave_sum(phi);
+        if (lane == 0 && valid && !b.probe_pass) b.phi_part[(size_t)j * 4 + wc] = phi;
+      }
+      __syncthreads();
+      // adjoint and in-place update, column tiles over every wave
+      double regP = 0.0, regO = 0.0;
+      if (b.norm) {
+        regP = b.alpha * (double)__uint_as_float(b.winmax[2 * j]);
+        regO = b.alpha * (double)__uint_as_float(b.winmax[2 * j + 1]);
+      }
+      UpdateSink sink{b.O, b.P, b.n, b.W, ps.x, ps.y, b.norm, b.probe_step, (int)valid, b.probe_pass,
+                      b.inv_n2, b.beta, b.gamma, regP, regO};
+      ResSrc rsrc{b.R, b.m};
+      for (int kt2 = w; kt2 < b.nb; kt2 += kSeqWaves) adj_engine<PR, MT>(rsrc, b.nb, FT, kt2, sink);
+      __syncthreads();
+    }
+  }
+}
+
+// The same sequential sweep with everything it touches held in LDS: the
+// object over the scan's bounding box, the probe, the residual and both
+// twiddle tables are loaded once, every position reads and updates them
+// there, and the end of the sweep computes the statistics (against the
+// object still in global memory) before writing the box back.  One launch
+// per sweep; used when these fit the compute unit's LDS.
+struct SeqLdsLayout {
+  size_t obj, probe, res, fa, ft, pos, jidx, total;
+};
+
+__host__ __device__ inline SeqLdsLayout seq_lds_layout(int bb_h, int bb_w, int n, int m, int J, size_t fa_bytes,
+                                                         size_t ft_bytes) {
+  SeqLdsLayout L;
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  L.fa = 0;
+  L.ft = up(fa_bytes);
+  L.obj = L.ft + up(ft_bytes);
+  L.probe = L.obj + up((size_t)bb_h * bb_w * 8);
+  L.res = L.probe + up((size_t)n * n * 8);
+  L.pos = L.res + up((size_t)m * m * 8);
+  L.jidx = L.pos + up((size_t)J * 8);
+  L.total = L.jidx + up((size_t)J * 4);
+  return L;
+}
+
+template <class PR, int MT, bool EXACT>
+__global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a, size_t fa_bytes, size_t ft_bytes) {
+  constexpr int CT = (MT <= 2) ? MT : 2;
+  constexpr int WC = (MT + CT - 1) / CT;
+  constexpr int WR = pie_wr<MT>();
+  static_assert(WR * WC <= kSeqWaves, "the forward's waves must fit the workgroup");
+  extern __shared__ f32x4 dyn[];
+  __shared__ f32x4 part[(WR > 1 ? (WR - 1) * WC : 1) * MT * CT * 2 * 64];
+  __shared__ double red[kSeqWaves][4];
+  __shared__ unsigned wmx[2][2];  // per-position max |P|^2, max |O_j|^2 (double-buffered by position parity)
+  char* base = reinterpret_cast<char*>(dyn);
+  const SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes);
+  float2* Ol = reinterpret_cast<float2*>(base + L.obj);
+  float2* Pl = reinterpret_cast<float2*>(base + L.probe);
+  float2* Rl = reinterpret_cast<float2*>(base + L.res);
+  int2* posl = reinterpret_cast<int2*>(base + L.pos);  // window corner in the box, x < 0: no position
+  int* jl = reinterpret_cast<int*>(base + L.jidx);     // position index of each step
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int w = tid >> 6;
+  const int lane = lane_id();
+  // load: tables (verbatim), probe, object box, the order's positions;
+  // clear the per-position slots
+  {
+    const f32x4* fa = static_cast<const f32x4*>(a.fa);
+    const f32x4* ft = static_cast<const f32x4*>(a.ft);
+    f32x4* fal = reinterpret_cast<f32x4*>(base + L.fa);
+    f32x4* ftl = reinterpret_cast<f32x4*>(base + L.ft);
+    for (size_t i = tid; i < fa_bytes / 16; i += nt) fal[i] = fa[i];
+    for (size_t i = tid; i < ft_bytes / 16; i += nt) ftl[i] = ft[i];
+    for (int i = tid; i < a.n * a.n; i += nt) Pl[i] = a.P[i];
+    for (int i = tid; i < a.bb_h * a.bb_w; i += nt)
+      Ol[i] = a.O[(size_t)(a.bb_r0 + i / a.bb_w) * a.W + a.bb_c0 + i % a.bb_w];
+    for (int t = tid; t < a.J; t += nt) {
+      bool valid;
+      const int j = pos_index(a.order, a.J, t, 0, &valid);
+      const int2 ps = a.pos[j];
+      posl[t] = valid ? make_int2(ps.x - a.bb_r0, ps.y - a.bb_c0) : make_int2(-1, 0);
+      jl[t] = j;
+    }
+    for (int i = tid; i < a.J * 4; i += nt) a.phi_part[i] = 0.0;
+    if (tid < 4) wmx[tid >> 1][tid & 1] = 0u;
+  }
+  __syncthreads();
+  const TabL FA{(lds_cptr)(base + L.fa)};
+  const TabL FT{(lds_cptr)(base + L.ft)};
+  const int wc = w % WC, wr = w / WC;
+  const bool fwd_wave = w < WR * WC;
+  const int passes = a.probe_literal ? 2 : 1;
+  const int m = a.m;
+  for (int t = 0; t < a.J; ++t) {
+    const int2 rc0 = posl[t];
+    const bool valid = rc0.x >= 0;
+    const int j = jl[t];
+    const int r = valid ? rc0.x : 0, c = rc0.y;
+    unsigned* mx = wmx[t & 1];
+    if (tid == 0) {  // the next position's maxima start from zero (last read two positions ago)
+      wmx[(t + 1) & 1][0] = 0u;
+      wmx[(t + 1) & 1][1] = 0u;
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+      PieArgs b = a;
+      b.R = Rl;
+      if (a.probe_literal) {
+        b.probe_step = pass;
+        b.probe_pass = pass;
+      }
+      const bool track = b.norm || b.probe_step;
+      // the projection's amplitudes, requested before the products
+      float av[MT][CT][4];
+      if (fwd_wave && wr == 0) {
+#pragma unroll
+        for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
+              av[c1t][ct][i] = (rc.x < m && rc.y < m) ? a.amp[(size_t)j * m * m + (size_t)rc.x * m + rc.y] : 0.f;
+            }
+      }
+      f32x4 Yre[MT][CT], Yim[MT][CT];
+      if (fwd_wave) {
+        if (track) {
+          GatherTrackSrc<EXACT> src{{Ol, Pl, a.bb_w, b.n, r, c}, 0.f, 0.f};
+          fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
+          if (wc == 0) {
+            const float mp = wave_max(src.mp), mo = wave_max(src.mo);
+            if (lane == 0) {
+              atomicMax(&mx[0], __float_as_uint(mp));
+              atomicMax(&mx[1], __float_as_uint(mo));
+            }
+          }
+        } else {
+          GatherSrc<EXACT> src{Ol, Pl, a.bb_w, b.n, r, c};
+          fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
+        }
+        if (WR > 1 && wr > 0) {
+          f32x4* dst = part + ((size_t)((wr - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+          for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+            for (int b1 = 0; b1 < CT; ++b1) {
+              dst[((a1 * CT + b1) * 2 + 0) * 64 + lane] = Yre[a1][b1];
+              dst[((a1 * CT + b1) * 2 + 1) * 64 + lane] = Yim[a1][b1];
+            }
+        }
+      }
+      __syncthreads();
+      if (fwd_wave && wr == 0) {
+#pragma unroll
+        for (int rr = 1; rr < WR; ++rr) {
+          const f32x4* src = part + ((size_t)((rr - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+          for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+            for (int b1 = 0; b1 < CT; ++b1) {
+              Yre[a1][b1] += src[((a1 * CT + b1) * 2 + 0) * 64 + lane];
+              Yim[a1][b1] += src[((a1 * CT + b1) * 2 + 1) * 64 + lane];
+            }
+        }
+        double phi = 0.0;
+#pragma unroll
+        for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
+              if (rc.x < m && rc.y < m)
+                phi += pie_project_amp(b, 0, valid, rc.x, rc.y, Yre[c1t][ct][i], Yim[c1t][ct][i], av[c1t][ct][i]);
+            }
+        phi = wave_sum(phi);
+        if (lane == 0 && valid && !b.probe_pass) b.phi_part[(size_t)j * 4 + wc] = phi;
+      }
+      __syncthreads();
+      double regP = 0.0, regO = 0.0;
+      if (b.norm) {
+        regP = b.alpha * (double)__uint_as_float(mx[0]);
+        regO = b.alpha * (double)__uint_as_float(mx[1]);
+      }
+      UpdateSink sink{Ol, Pl, b.n, a.bb_w, r, c, b.norm, b.probe_step, (int)valid, b.probe_pass,
+                      b.inv_n2, b.beta, b.gamma, regP, regO};
+      ResSrc rsrc{Rl, m};
+      for (int kt2 = w; kt2 < b.nb; kt2 += kSeqWaves) adj_engine<PR, MT>(rsrc, b.nb, FT, kt2, sink);
+      __syncthreads();
+    }
+  }
+  // statistics against the object still in global memory, then write back:
+  // {Phi, ||O_after - O_before||^2, ||O_before||^2, non-finite}
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = tid; i < a.J * 4; i += nt) v[0] += a.phi_part[i];
+  const size_t total = (size_t)a.H * a.W;
+  for (size_t i = tid; i < total; i += nt) {
+    const int y = (int)(i / a.W), x = (int)(i % a.W);
+    const float2 z = a.O[i];
+    float2 o = z;
+    const int yy = y - a.bb_r0, xx = x - a.bb_c0;
+    if (yy >= 0 && yy < a.bb_h && xx >= 0 && xx < a.bb_w) o = Ol[(size_t)yy * a.bb_w + xx];
+    const double dx = (double)o.x - z.x, dy = (double)o.y - z.y;
+    v[1] += dx * dx + dy * dy;
+    v[2] += (double)z.x * z.x + (double)z.y * z.y;
+    v[3] += (isfinite(o.x) && isfinite(o.y)) ? 0.0 : 1.0;
+  }
+  if (a.probe_step)
+    for (int i = tid; i < a.n * a.n; i += nt) v[3] += (isfinite(Pl[i].x) && isfinite(Pl[i].y)) ? 0.0 : 1.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (tid == 0) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < kSeqWaves; ++k)
+      for (int q = 0; q < 4; ++q) s4[q] += red[k][q];
+    a.stats[0] = s4[0] / ((double)a.J * a.period * a.period);
+    a.stats[1] = s4[1];
+    a.stats[2] = s4[2];
+    a.stats[3] = s4[3];
+  }
+  for (int i = tid; i < a.bb_h * a.bb_w; i += nt)
+    a.O[(size_t)(a.bb_r0 + i / a.bb_w) * a.W + a.bb_c0 + i % a.bb_w] = Ol[i];
+  if (a.probe_step)
+    for (int i = tid; i < a.n * a.n; i += nt) a.P[i] = Pl[i];
+}
+
+template <class PR, int MT>
+bool sequential_lds_prec(const PieArgs& a, size_t fa_bytes, size_t ft_bytes, hipStream_t st) {
+  const SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes);
+  // (the statistics read the whole object from one workgroup)
+  if (L.total > kSeqLdsBytes || (size_t)a.H * a.W > kSeqLdsMaxObject) return false;
+  auto launch = [&](auto kernel) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)L.total) != hipSuccess)
+      return false;
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(64 * kSeqWaves), L.total, st, a, fa_bytes, ft_bytes);
+    return true;
+  };
+  return a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true>) : launch(k_pie_sequential_lds<PR, MT, false>);
+}
+
+template <class PR, int MT>
+void sequential_prec(const PieArgs& a, hipStream_t st) {
+  if (a.n % 16 == 0)
+    hipLaunchKernelGGL((k_pie_sequential<PR, MT, true>), dim3(1), dim3(64 * kSeqWaves), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_pie_sequential<PR, MT, false>), dim3(1), dim3(64 * kSeqWaves), 0, st, a);
+}
+
 template <class PR, int MT>
 static int fwd_split_blocks(bool rs) {
   constexpr int CT = (MT <= 2) ? MT : 2;
@@ -415,6 +775,24 @@ static int fwd_split_blocks_mt(int mt, bool rs) {
     case 7: return fwd_split_blocks<PR, 7>(rs);
     case 8: return fwd_split_blocks<PR, 8>(rs);
     default: return 1;
+  }
+}
+
+template <class PR>
+bool sequential_lds_dense(const PieArgs& a, size_t fa_bytes, size_t ft_bytes, hipStream_t st) {
+  switch (a.mt) {
+    case 1: return sequential_lds_prec<PR, 1>(a, fa_bytes, ft_bytes, st);
+    case 2: return sequential_lds_prec<PR, 2>(a, fa_bytes, ft_bytes, st);
+    default: return false;
+  }
+}
+
+template <class PR>
+void sequential_dense(const PieArgs& a, hipStream_t st) {
+  switch (a.mt) {
+    case 1: sequential_prec<PR, 1>(a, st); break;
+    case 2: sequential_prec<PR, 2>(a, st); break;
+    default: break;
   }
 }
 

@@ -158,6 +158,8 @@ pftpie_status sweep(pie_scan scan, void* object, void* probe, const float* amp, 
   a.fa = pl->fa;
   a.ft = pl->ft;
   a.fft_tw = pl->method == PFTPIE_METHOD_FFT ? static_cast<const float2*>(pl->fft_tw) : nullptr;
+  a.fa_bytes = pl->fa_bytes;
+  a.ft_bytes = pl->ft_bytes;
   a.prec = pl->prec;
   a.period = pl->period;
   a.inv_n2 = (float)(1.0 / ((double)pl->period * pl->period));

@@ -284,3 +284,26 @@ def test_noise_free_fixed_point_split(pk, tiny, precision, tol):
     O, _, _ = run_gpu(pk, tiny, tiny["obj"], tiny["probe"], A, tiny["m"],
                       pk.PieParams(batch=64, norm=1, beta=1.0, alpha=1e-3), precision=precision)
     assert rel(O, tiny["obj"]) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("split_fp16", 1e-5)])
+@pytest.mark.parametrize("params", [dict(batch=1, norm=0, beta=1.0, gamma=0.3),
+                                    dict(batch=1, norm=1, beta=1.0, alpha=0.1)], ids=["plain", "norm"])
+def test_sequential_sweep_on_a_large_object(pk, precision, tol, params):
+    """Sequential sweeps of small windows run in one persistent workgroup;
+    an object too large for it to hold (300 x 300) takes the variant that
+    updates global memory: both match the oracle, as the LDS variant does on
+    the tiny workload (the other sequential tests)."""
+    print("pie sequential large object", precision, params, flush=True)
+    rng = np.random.default_rng(8)
+    H = W = 300
+    n, m = 32, 16
+    obj = (rng.uniform(0.5, 1, (H, W)) * np.exp(1j * rng.uniform(-1, 1, (H, W)))).astype(np.complex64)
+    probe = workloads.gaussian_probe(n, 6.0, np.pi / 144.0)
+    pos = workloads.raster(5, 5, 20, 90)
+    case = dict(pos=pos, probe=probe)
+    amp = np.abs(rng.standard_normal((len(pos), m, m))).astype(np.float32) * 40
+    O, P, st = run_gpu(pk, case, obj, probe, amp, m, pk.PieParams(**params), precision=precision)
+    Or, Pr, sr = opie.pie_sweep(obj, probe, pos, amp, m, **params)
+    assert rel(O, Or) <= tol and rel(P, Pr) <= tol
+    assert abs(st[0][0] - sr[0]) <= tol * sr[0] and abs(st[0][1] - sr[1]) <= 1e-4 * sr[1]
