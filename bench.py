@@ -400,8 +400,9 @@ def recon_study(torch, pk, precision="fp32", hybrid=True, iters_pft=50, iters_fu
 
 def group_rate(torch, pk, precisions, steps=5, warmup=2):
     """Uneven batch: 8192 descriptors, n in {64,128,256,512}, m = n/4, one
-    persistent launch per call (graph replay).  Inputs drawn on the device
-    (seeded); correctness of this path is covered by the parity tests."""
+    persistent launch per call (graph replay), timed before and after the
+    group's autotuner.  Inputs drawn on the device (seeded); correctness of
+    this path is covered by the parity tests."""
     import workloads
     d, tin, tout = workloads.grouped_descs()
     g = torch.Generator(device="cuda")
@@ -413,9 +414,11 @@ def group_rate(torch, pk, precisions, steps=5, warmup=2):
     out = {}
     for p in precisions:
         grp = pk.Group(d, tin, tout, p)
+        ms0 = time_calls(torch, lambda: grp.run(x, y), steps, warmup)
+        grp.autotune()                      # the group's own launch choices, on random inputs
         ms = time_calls(torch, lambda: grp.run(x, y), steps, warmup)
-        out[p] = {"forward_ms": ms, "patches_per_s": len(d) / ms * 1e3, "tflops_alg": flops / ms / 1e9,
-                  "gbs_alg": byts / ms / 1e6}
+        out[p] = {"forward_ms": ms, "forward_ms_untuned": ms0, "patches_per_s": len(d) / ms * 1e3,
+                  "tflops_alg": flops / ms / 1e9, "gbs_alg": byts / ms / 1e6}
         grp.close()
     del x, y
     return out

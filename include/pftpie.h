@@ -238,6 +238,16 @@ pftpie_status pftpie_group_destroy(pft2d_group group);
 /* Run the whole uneven batch (all plans share one precision).  in / out:
  * device complex64 packed arrays. */
 pftpie_status pft2d_group_run(pft2d_group group, const void* in, void* out, void* stream);
+/* Autotuner of the group's own launch choices, timed on its real
+ * descriptor mix with random inputs (uniform in [-1, 1)): per (n, m) class,
+ * largest work first, the forward column tiles per wave (1 or 2) or the
+ * adjoint column tiles per work item (1, 2, 4 or 8), then the workgroups
+ * per compute unit (1..4); each choice is kept when it lowers the batch
+ * time.  Rebuilds the work list and the graph with the result; allocates
+ * and frees scratch and synchronises the device.  best_ms (may be NULL):
+ * the best batch time.  Results keep their definition (only the order of
+ * float sums changes). */
+pftpie_status pftpie_group_autotune(pft2d_group group, double* best_ms);
 
 /* ------------------------------------------------------------------------ */
 /* PIE / ePIE sweep (Sec. 2.1: projection eq. (3), objective eq. (4), object

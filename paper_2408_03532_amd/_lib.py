@@ -58,6 +58,7 @@ SIGNATURES = {
                                   ctypes.POINTER(c_group)]),
     "pftpie_group_destroy": (i32, [c_group]),
     "pft2d_group_run": (i32, [c_group, vp, vp, vp]),
+    "pftpie_group_autotune": (i32, [c_group, ctypes.POINTER(ctypes.c_double)]),
     "pftpie_measure_mfma_peaks": (i32, [ctypes.POINTER(ctypes.c_double)] * 3),
     "pft2d_grouped_workspace_size": (i32, [ctypes.POINTER(Desc), i64, i32, ctypes.POINTER(sz)]),
     "pft2d_forward_grouped": (i32, [ctypes.POINTER(Desc), i64, vp, vp, i32, vp, sz, vp]),

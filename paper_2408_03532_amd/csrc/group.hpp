@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "internal.hpp"
 
 namespace pftpie {
@@ -43,6 +45,15 @@ constexpr int kGroupThreads = 256;
 
 struct pft2d_group_s {
   int prec, adjoint, device, num_cu;
+  // descriptors and plans (kept for the autotuner) and the per-class launch
+  // choices it may change: forward column tiles per wave, adjoint column
+  // tiles per item (0: the default), workgroups per compute unit
+  std::vector<pft2d_desc> descs;
+  std::vector<pftpie_plan_s*> plans;
+  int ct_choice[pftpie::kGroupMaxClasses];
+  int kpi_choice[pftpie::kGroupMaxClasses];
+  int wg_per_cu;
+  size_t items_cap;                // work items the device list can hold
   pftpie::GroupArgs args;      // in / out filled at run time
   pftpie::GroupItem* items;    // device
   unsigned long long* counter; // device

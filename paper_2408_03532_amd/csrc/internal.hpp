@@ -64,6 +64,10 @@ void register_plan(pftpie_plan_s* p);
 void unregister_plan(pftpie_plan_s* p);
 pftpie_plan_s* find_plan(int n, int m, pftpie_precision prec, int device);
 
+// Fills x[0, count) with float pairs uniform in [-1, 1) (timing operands of
+// the autotuners; zeros would run the matrix cores at another clock).
+hipError_t tune_fill(float2* x, size_t count, uint32_t salt, hipStream_t st);
+
 // Thread-local error message plumbing.
 pftpie_status fail(pftpie_status s, const std::string& msg);
 pftpie_status hip_fail(hipError_t e, const char* where);

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_tune_fill(float2* __restrict__ x, size_
   }
 }
 
-static hipError_t tune_fill(float2* x, size_t count, uint32_t salt, hipStream_t st) {
+hipError_t tune_fill(float2* x, size_t count, uint32_t salt, hipStream_t st) {
   size_t blocks = (count + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;

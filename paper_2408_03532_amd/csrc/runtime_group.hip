@@ -33,7 +33,8 @@ struct Work {
 // in_len / out_len < 0: no packed-array lengths given; the extents the
 // descriptors reach are returned instead.
 pftpie_status build_work(const pftpie_plan_s* const* plans, int nplans, const pft2d_desc* desc, int64_t count,
-                         int64_t in_len, int64_t out_len, int adjoint, const std::string& who, Work& w) {
+                         int64_t in_len, int64_t out_len, int adjoint, const std::string& who, Work& w,
+                         const int* ct_choice = nullptr, const int* kpi_choice = nullptr) {
   if (nplans < 1 || nplans > kGroupMaxClasses) return fail(PFTPIE_E_INVALID, who + ": need 1..8 (n, m) classes");
   for (int k = 0; k < nplans; ++k) {
     if (!plans[k]) return fail(PFTPIE_E_INVALID, who + ": NULL plan");
@@ -55,8 +56,10 @@ pftpie_status build_work(const pftpie_plan_s* const* plans, int nplans, const pf
     c.nb = p->nb;
     c.mt = p->mt;
     c.ct = (p->fwd_ct == 1 || p->mt == 1) ? 1 : 2;
+    if (ct_choice && ct_choice[k] > 0) c.ct = (ct_choice[k] == 2 && p->mt >= 2) ? 2 : 1;
     c.w = (c.mt + c.ct - 1) / c.ct;
     c.kpi = 4;
+    if (kpi_choice && kpi_choice[k] > 0) c.kpi = kpi_choice[k];
     c.tab = adjoint ? p->ft : p->fa;
     if (p->n % 16) exact[k] = 0;
   }
@@ -110,8 +113,16 @@ pftpie_status build_work(const pftpie_plan_s* const* plans, int nplans, const pf
   return PFTPIE_OK;
 }
 
-unsigned grid_for(int num_cu, int64_t nitems) {
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)num_cu * 2, (nitems + 3) / 4));
+unsigned grid_for(int num_cu, int64_t nitems, int wg_per_cu = 2) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)num_cu * wg_per_cu, (nitems + 3) / 4));
+}
+
+// The most work items any launch choice gives these descriptors: forward
+// one per column tile, adjoint one per column tile.
+size_t items_bound(const pft2d_desc* desc, int64_t count) {
+  size_t items = 0;
+  for (int64_t i = 0; i < count; ++i) items += (size_t)std::max(ceil16(desc[i].m), ceil16(desc[i].n));
+  return items;
 }
 
 hipKernelNodeParams kernel_node(pft2d_group_s* g, void** kargs) {
@@ -249,8 +260,13 @@ pftpie_status pftpie_group_create(const pftpie_plan* plans, int32_t nplans, cons
   g->nitems = (int64_t)w.items.size();
   g->in_len = in_len;
   g->out_len = out_len;
-  g->grid = grid_for(g->num_cu, g->nitems);
-  hipError_t e = hipMalloc((void**)&g->items, sizeof(GroupItem) * std::max<size_t>(1, w.items.size()));
+  g->wg_per_cu = 2;
+  for (int k = 0; k < kGroupMaxClasses; ++k) g->ct_choice[k] = g->kpi_choice[k] = 0;
+  g->descs.assign(host_desc, host_desc + count);
+  g->plans.assign(plans, plans + nplans);
+  g->items_cap = std::max<size_t>(1, items_bound(host_desc, count));
+  g->grid = grid_for(g->num_cu, g->nitems, g->wg_per_cu);
+  hipError_t e = hipMalloc((void**)&g->items, sizeof(GroupItem) * g->items_cap);
   if (e == hipSuccess) e = hipMalloc((void**)&g->counter, sizeof(unsigned long long));
   if (e != hipSuccess) {
     destroy_group(g);
@@ -305,6 +321,137 @@ pftpie_status pft2d_group_run(pft2d_group g, const void* in, void* out, void* st
   }
   e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, "group_run: graph launch");
+}
+
+pftpie_status pftpie_group_autotune(pft2d_group g, double* best_ms) {
+  if (!g) return fail(PFTPIE_E_INVALID, "group_autotune: group is NULL");
+  if (g->nitems == 0) {
+    if (best_ms) *best_ms = 0.0;
+    return PFTPIE_OK;
+  }
+  const int nplans = (int)g->plans.size();
+  float2 *x = nullptr, *y = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc((void**)&x, std::max<int64_t>(1, g->in_len) * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&y, std::max<int64_t>(1, g->out_len) * 8);
+  if (e == hipSuccess) e = hipStreamCreate(&st);
+  if (e == hipSuccess) e = tune_fill(x, (size_t)g->in_len, 0x2468aceu, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(x);
+    (void)hipFree(y);
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(PFTPIE_E_NOMEM, std::string("group_autotune: scratch: ") + hipGetErrorString(e));
+  }
+  // time the batch with launch choices (ct, kpi, wg): rebuild the work
+  // list, upload it, run reset + kernel directly (best of 3 after a warm-up)
+  auto time_with = [&](const int* ct, const int* kpi, int wg, Work& w) -> double {
+    w = Work{};
+    if (build_work(g->plans.data(), nplans, g->descs.data(), (int64_t)g->descs.size(), g->in_len, g->out_len,
+                   g->adjoint, "group_autotune", w, ct, kpi) != PFTPIE_OK)
+      return 1e30;
+    if (w.items.size() > g->items_cap) return 1e30;
+    if (hipMemcpyAsync(g->items, w.items.data(), sizeof(GroupItem) * w.items.size(), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return 1e30;
+    w.args.items = g->items;
+    w.args.counter = g->counter;
+    w.args.in = x;
+    w.args.out = y;
+    void* kargs[] = {&w.args};
+    const unsigned grid = grid_for(g->num_cu, w.args.nitems, wg);
+    double best = 1e30;
+    for (int rep = 0; rep < 4; ++rep) {
+      (void)hipEventRecord(e0, st);
+      hipLaunchKernelGGL(reinterpret_cast<void (*)(unsigned long long*)>(group_reset_kernel()), dim3(1), dim3(64), 0,
+                         st, g->counter);
+      hipError_t le = hipLaunchKernel(group_kernel(g->prec, g->adjoint), dim3(grid), dim3(kGroupThreads), kargs, 0, st);
+      (void)hipEventRecord(e1, st);
+      if (le != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, (double)ms);
+    }
+    return best;
+  };
+  int ct[kGroupMaxClasses], kpi[kGroupMaxClasses];
+  for (int k = 0; k < kGroupMaxClasses; ++k) {
+    ct[k] = g->ct_choice[k];
+    kpi[k] = g->kpi_choice[k];
+  }
+  int wg = g->wg_per_cu;
+  Work w;
+  double best = time_with(ct, kpi, wg, w);
+  // classes in order of their work (longest first), one choice at a time
+  std::vector<std::pair<double, int>> order;
+  for (int k = 0; k < nplans; ++k) {
+    double work = 0.0;
+    for (const pft2d_desc& d : g->descs)
+      if (d.n == g->plans[k]->n && d.m == g->plans[k]->m) work += (double)d.n * d.m * (d.n + d.m);
+    order.push_back({-work, k});
+  }
+  std::sort(order.begin(), order.end());
+  for (const auto& o : order) {
+    const int k = o.second;
+    static const int kAdjOpts[] = {1, 2, 4, 8};
+    static const int kFwdOpts[] = {1, 2};
+    const int* opts = g->adjoint ? kAdjOpts : kFwdOpts;
+    const int nopts = g->adjoint ? 4 : 2;
+    for (int i = 0; i < nopts; ++i) {
+      int* choice = g->adjoint ? kpi : ct;
+      const int keep = choice[k];
+      choice[k] = opts[i];
+      const double t = time_with(ct, kpi, wg, w);
+      if (t < best) {
+        best = t;
+      } else {
+        choice[k] = keep;
+      }
+    }
+  }
+  for (int cand : {1, 2, 3, 4}) {
+    const double t = time_with(ct, kpi, cand, w);
+    if (t < best) {
+      best = t;
+      wg = cand;
+    }
+  }
+  // keep the best choices: work list, grid and graph
+  for (int k = 0; k < kGroupMaxClasses; ++k) {
+    g->ct_choice[k] = ct[k];
+    g->kpi_choice[k] = kpi[k];
+  }
+  g->wg_per_cu = wg;
+  Work fin;
+  pftpie_status rs = build_work(g->plans.data(), nplans, g->descs.data(), (int64_t)g->descs.size(), g->in_len,
+                                g->out_len, g->adjoint, "group_autotune", fin, ct, kpi);
+  if (rs == PFTPIE_OK &&
+      (e = hipMemcpy(g->items, fin.items.data(), sizeof(GroupItem) * fin.items.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    rs = hip_fail(e, "group_autotune: upload");
+  cleanup();
+  if (rs != PFTPIE_OK) return rs;
+  g->args = fin.args;
+  g->args.items = g->items;
+  g->args.counter = g->counter;
+  g->nitems = (int64_t)fin.items.size();
+  g->grid = grid_for(g->num_cu, g->nitems, g->wg_per_cu);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+  g->graph_in = nullptr;
+  g->graph_out = nullptr;
+  if ((e = build_graph(g)) != hipSuccess) return hip_fail(e, "group_autotune: graph");
+  if (best >= 1e30) return fail(PFTPIE_E_DEVICE, "group_autotune: every candidate failed");
+  if (best_ms) *best_ms = best;
+  return PFTPIE_OK;
 }
 
 pftpie_status pft2d_grouped_workspace_size(const pft2d_desc* host_desc, int64_t count, int32_t adjoint,

@@ -207,6 +207,14 @@ class Group:
         except Exception:
             pass
 
+    def autotune(self):
+        """Tune the group's launch choices on its descriptor mix (random
+        inputs); returns the best batch time in milliseconds."""
+        ms = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _lib.call("pftpie_group_autotune", self.handle, ctypes.byref(ms))
+        return ms.value
+
     def run(self, inp, out=None):
         _require(inp, "inp")
         if inp.numel() != self.in_len:

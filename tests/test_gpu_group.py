@@ -178,3 +178,28 @@ def test_autotuner_keeps_results(pk, tmp_path, monkeypatch):
     assert (tmp_path / "tune.txt").read_text().count("\n") == 1
     plan2 = pk.Plan(128, 32)
     assert pk.autotune(plan2, 64) == pytest.approx(ms)   # read back from the cache
+
+
+@pytest.mark.parametrize("prec", sorted(TOLS))
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_group_autotuner_keeps_results(pk, prec, adjoint):
+    """The group's own autotuner (per-class column tiles per wave or per
+    item, workgroups per compute unit, timed on random inputs of the real
+    descriptor mix) changes launch choices only: the tuned group matches
+    the untuned one and the oracle to the precision's tolerance."""
+    print("group autotune", prec, adjoint, flush=True)
+    d, tin, tout = mixed_descs(SMALL + [(512, 128)] * 2, seed=13)
+    if adjoint:
+        d, tin, tout = workloads.adjoint_descs(d), tout, tin
+    x = workloads.grouped_inputs(d, tin, seed=19, adjoint=adjoint)
+    g = pk.Group(d, tin, tout, prec, adjoint=adjoint)
+    xt = torch.from_numpy(x).cuda()
+    before = g.run(xt).cpu().numpy()
+    ms = g.autotune()
+    assert ms > 0
+    after = g.run(xt).cpu().numpy()
+    # another tile split changes the float summation order (and in FP32 may
+    # switch between the three- and four-product forms): within tolerance
+    assert rel(after, before) <= TOLS[prec]
+    ref = opft.grouped_adjoint(d, x, tout) if adjoint else opft.grouped_forward(d, x, tout)
+    assert rel(after, ref) <= TOLS[prec]
