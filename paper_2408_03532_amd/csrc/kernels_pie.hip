@@ -46,6 +46,35 @@ bool pie_sequential_lds_f16(const PieArgs& a, hipStream_t st);
 // ---------------------------------------------------------------------------
 // gathers of a chunk's corrections
 
+// Sums of three doubles over the workgroup (fixed order), stored by thread 0
+// at out[0..2].
+__device__ __forceinline__ void block_sum3(double v0, double v1, double v2, double* out) {
+  __shared__ double sh3[3][16];
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh3[0][w] = v0;
+    sh3[1][w] = v1;
+    sh3[2][w] = v2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh3[threadIdx.x][k];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ||new - old||^2, ||old||^2 and non-finite count of one pixel's update.
+__device__ __forceinline__ void pixel_stats(float2 ov, float2 nv, double& d2, double& o2, double& bad) {
+  const double dx = (double)nv.x - ov.x, dy = (double)nv.y - ov.y;
+  d2 += dx * dx + dy * dy;
+  o2 += (double)ov.x * ov.x + (double)ov.y * ov.y;
+  bad += (isfinite(nv.x) && isfinite(nv.y)) ? 0.0 : 1.0;
+}
+
 __device__ __forceinline__ double block_max(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -166,7 +195,19 @@ __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, in
   }
   const size_t o = (size_t)py * a.W + px;
   if (!a.norm) {
-    if (inside && (acc.x != 0.f || acc.y != 0.f)) {
+    if (a.fuse_stats) {
+      double d2 = 0.0, o2 = 0.0, bad = 0.0;
+      if (inside) {
+        const float2 ov = a.O[o];
+        float2 nv = ov;
+        if (acc.x != 0.f || acc.y != 0.f) {
+          nv = make_float2(ov.x + a.beta * acc.x, ov.y + a.beta * acc.y);
+          a.O[o] = nv;
+        }
+        pixel_stats(ov, nv, d2, o2, bad);
+      }
+      block_sum3(d2, o2, bad, a.fred + (size_t)tile * 3);
+    } else if (inside && (acc.x != 0.f || acc.y != 0.f)) {
       const float2 ov = a.O[o];
       a.O[o] = make_float2(ov.x + a.beta * acc.x, ov.y + a.beta * acc.y);
     }
@@ -207,6 +248,7 @@ __global__ __launch_bounds__(256) void k_pie_reduce_max(PieArgs a, int nprobe_bl
 __global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
   if (object_part) {
     const double regO = a.alpha * a.maxes[0];
+    double d2 = 0.0, o2 = 0.0, bad = 0.0;
     // rows of the bounding box over blockIdx.y, columns over blockIdx.x
     for (int rr = blockIdx.y; rr < a.bb_h; rr += gridDim.y)
     for (int cc = blockIdx.x * blockDim.x + threadIdx.x; cc < a.bb_w; cc += gridDim.x * blockDim.x) {
@@ -216,9 +258,15 @@ __global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
         const float sc = (float)((double)a.beta / (d + regO));
         const float2 num = a.numO[o];
         const float2 ov = a.O[o];
-        a.O[o] = make_float2(ov.x + sc * num.x, ov.y + sc * num.y);
+        const float2 nv = make_float2(ov.x + sc * num.x, ov.y + sc * num.y);
+        a.O[o] = nv;
+        if (a.fuse_stats) pixel_stats(ov, nv, d2, o2, bad);
+      } else if (a.fuse_stats) {
+        const float2 ov = a.O[o];
+        pixel_stats(ov, ov, d2, o2, bad);
       }
     }
+    if (a.fuse_stats) block_sum3(d2, o2, bad, a.fred + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 3);
   }
   if (a.probe_step) {
     const size_t nn = (size_t)a.n * a.n;
@@ -246,7 +294,8 @@ __global__ __launch_bounds__(256) void k_pie_begin(PieArgs a) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t total = (size_t)a.H * a.W;
-  for (size_t t = t0; t < total; t += stride) a.O0[t] = a.O[t];
+  if (!a.fuse_stats)
+    for (size_t t = t0; t < total; t += stride) a.O0[t] = a.O[t];
   for (size_t t = t0; t < (size_t)a.J; t += stride) {
     a.rank[t] = a.order ? kRankAbsent : (int)t;
     a.winmax[2 * t] = 0u;
@@ -272,11 +321,16 @@ __global__ __launch_bounds__(256) void k_pie_stats_part(PieArgs a) {
   const size_t total = (size_t)a.H * a.W;
   double d2 = 0.0, o2 = 0.0, bad = 0.0;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    if (a.fuse_stats) {
+      // the box was summed by the update; outside it the object is unchanged
+      const int y = (int)(t / a.W) - a.bb_r0, x = (int)(t % a.W) - a.bb_c0;
+      if (y >= 0 && y < a.bb_h && x >= 0 && x < a.bb_w) continue;
+      const float2 z = a.O[t];
+      pixel_stats(z, z, d2, o2, bad);
+      continue;
+    }
     const float2 o = a.O[t], z = a.O0[t];
-    const double dx = (double)o.x - z.x, dy = (double)o.y - z.y;
-    d2 += dx * dx + dy * dy;
-    o2 += (double)z.x * z.x + (double)z.y * z.y;
-    bad += (isfinite(o.x) && isfinite(o.y)) ? 0.0 : 1.0;
+    pixel_stats(z, o, d2, o2, bad);
   }
   if (a.probe_step) {
     const size_t nn = (size_t)a.n * a.n;
@@ -303,13 +357,15 @@ __global__ __launch_bounds__(256) void k_pie_stats_part(PieArgs a) {
 }
 
 // stats = {Phi, ||dO||^2, ||O||^2, non-finite}: one wave, fixed order.
-__global__ __launch_bounds__(1024) void k_pie_stats_final(PieArgs a, int nblocks) {
+__global__ __launch_bounds__(1024) void k_pie_stats_final(PieArgs a, int nblocks, int nfused) {
   __shared__ double sh[4][16];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const size_t np = (size_t)a.J * 4;
   for (size_t t = threadIdx.x; t < np; t += blockDim.x) v[0] += a.phi_part[t];
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int c = 0; c < 3; ++c) v[c + 1] += a.red[(size_t)b * 3 + c];
+  for (int b = threadIdx.x; b < nfused; b += blockDim.x)
+    for (int c = 0; c < 3; ++c) v[c + 1] += a.fred[(size_t)b * 3 + c];
   for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if ((threadIdx.x & 63) == 0)
@@ -398,7 +454,7 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
     else
       pie_sequential_dense_f32(a, st);
     hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks);
+    hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks, 0);
     return hipGetLastError();
   }
   // eq. (6) as printed (single positions): the object step, then a second
@@ -406,6 +462,7 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   PieArgs obj_pass = a, probe_pass = a;
   obj_pass.probe_step = 0;
   probe_pass.probe_pass = 1;
+  int nfused = 0;  // statistics partials written by the update (single-chunk sweeps)
   for (int c0 = 0; c0 < a.J; c0 += batch) {
     const int cnt = (a.J - c0 < batch) ? a.J - c0 : batch;
     hipError_t e;
@@ -418,6 +475,7 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
     if (cnt == 1) continue;  // updated in place
     if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt);
     hipLaunchKernelGGL(k_pie_object_gather, dim3(ntiles), dim3(256), 0, st, a, c0, cnt);
+    if (a.fuse_stats && !a.norm) nfused = ntiles;
     if (a.norm) {
       const int items = ntiles > pblocks ? ntiles : pblocks;
       int rb = (items + 255) / 256;
@@ -437,10 +495,11 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
       const int pb = a.probe_step ? ew_blocks((size_t)a.n * a.n) : 1;
       if (gx * gy < pb) gy = (pb + gx - 1) / gx;
       hipLaunchKernelGGL(k_pie_apply, dim3(gx, gy), dim3(256), 0, st, a, a.norm);
+      if (a.fuse_stats && a.norm) nfused = gx * gy;
     }
   }
   hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks);
+  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks, nfused);
   return hipGetLastError();
 }
 

@@ -61,9 +61,16 @@ struct PieArgs {
   double* maxes;    // [2]
   double* red;      // [kStatBlocks][3] statistics partials
   double* stats;    // [4]
+  // single-chunk sweeps: the kernels that update the object also sum
+  // ||dO||^2, ||O||^2 and the non-finite count over the bounding box into
+  // fred[block][3], so no object copy is taken at the sweep start and the
+  // statistics pass reads only the pixels outside the box
+  int fuse_stats;
+  double* fred;     // [kFusedRedBlocks or tiles][3]
 };
 
 constexpr int kStatBlocks = 2048;
+constexpr int kFusedRedBlocks = 4096 + 64;  // the most workgroups k_pie_apply launches
 constexpr int32_t kRankAbsent = 0x7fffffff;
 // Sequential sweeps (chunks of one position) of windows up to kSeqMaxNb
 // tiles of 16 per axis and up to 32 kept coefficients run in one

@@ -24,7 +24,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace carve-up of one sweep; sizes in bytes, offsets 256-aligned.
 struct PieLayout {
-  size_t R, part, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxpart, maxes, red, stats, total;
+  size_t R, part, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxpart, maxes, red, stats, fred, total;
+  int fuse;
   int splits;
 };
 
@@ -53,7 +54,10 @@ PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
   L.phi = take((size_t)s->J * 4 * 8);
   L.rank = take((size_t)s->J * 4);
   L.winmax = take((size_t)s->J * 8);
-  L.O0 = take(obj * 8);
+  // one chunk of several positions: statistics fused into the update, no
+  // object copy
+  L.fuse = multi && batch >= s->J;
+  L.O0 = L.fuse ? SIZE_MAX : take(obj * 8);
   L.numO = (multi && norm) ? take(obj * 8) : SIZE_MAX;
   L.D = (multi && norm) ? take(obj * 8) : SIZE_MAX;
   L.numP = (multi && probe_step) ? take(nn * 8) : SIZE_MAX;
@@ -62,6 +66,7 @@ PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
   L.maxes = take(16);
   L.red = take((size_t)kStatBlocks * 3 * 8);
   L.stats = take(32);
+  L.fred = L.fuse ? take((size_t)std::max<size_t>((size_t)s->tiles_x * s->tiles_y, kFusedRedBlocks) * 3 * 8) : SIZE_MAX;
   L.total = off;
   return L;
 }
@@ -190,6 +195,8 @@ pftpie_status sweep(pie_scan scan, void* object, void* probe, const float* amp, 
   a.maxes = static_cast<double*>(at(L.maxes));
   a.red = static_cast<double*>(at(L.red));
   a.stats = stats_dev ? stats_dev : static_cast<double*>(at(L.stats));
+  a.fuse_stats = L.fuse;
+  a.fred = static_cast<double*>(at(L.fred));
   hipError_t e = launch_pie_sweep(a, batch, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, (name + ": launch").c_str());
 }
