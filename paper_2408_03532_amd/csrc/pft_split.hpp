@@ -190,6 +190,14 @@ __device__ __forceinline__ void fwd_wave_split_pass(const Src& src, int NB, cons
     __builtin_amdgcn_sched_barrier(0);
     op[(u + 1) & 1] = split_c4<PR, false>(combine(src, a[(u + 1) % RING]));
     products(op[u & 1], f[u & 1]);
+    // one wave per SIMD: its vector work overlaps the matrix products only
+    // when issued between them, so the scheduler alternates one product
+    // with two vector instructions of the next chunk's split
+#pragma unroll
+    for (int k = 0; k < 6 * CT; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+    }
   };
   auto start = [&](auto load_a, auto load_f) {
 #pragma unroll
