@@ -1,7 +1,7 @@
 """Benchmark of the batched partial transform and the PIE sweep on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
-    python bench.py --workload {pft,group,pie,loss,peaks} [--precision P] [--steps K]
+    python bench.py --workload {pft,group,pie,loss,peaks,masked,tiny} [--precision P] [--steps K]
 
 Headline workload: the standalone batched transform, 4096 complex64 patches
 of 256 x 256 (Re/Im iid N(0,1), seeded), keeping the centred m = 64
@@ -91,7 +91,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", default=None, choices=["pft", "group", "pie", "loss", "peaks"],
+    ap.add_argument("--workload", default=None,
+                    choices=["pft", "group", "pie", "loss", "peaks", "masked", "tiny"],
                     help="run only this workload's kernels (profiling)")
     return ap.parse_args()
 
@@ -312,10 +313,13 @@ def fft_crop_rate(torch, x, m, y_ref, steps=5, warmup=2):
     def run():
         out["y"] = torch.fft.fft2(x)[:, idx][:, :, idx]
     ms = time_calls(torch, run, steps, warmup)
-    y = out.pop("y")
-    d = float(torch.linalg.vector_norm(y[:64] - y_ref[:64]) / torch.linalg.vector_norm(y_ref[:64]))
-    del y
+    del out["y"]
+    # the check runs on its own first 64 patches, after the timing
+    y = torch.fft.fft2(x[:64])[:, idx][:, :, idx]
+    ref = y_ref[:64].clone()
+    d = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
     return {"ms": ms, "patches_per_s": x.shape[0] / (ms * 1e-3), "rel_diff_vs_pft2d_forward": d,
+            "norms": [float(torch.linalg.vector_norm(y)), float(torch.linalg.vector_norm(ref))],
             "note": "context only: full transform then crop (rocFFT through torch), not a product path"}
 
 
@@ -445,6 +449,11 @@ def workload_only(torch, pk, args):
         out.update(pie_at_scale_rate(torch, pk, prec, sweeps=args.steps, warmup=1))
     elif args.workload == "loss":
         out.update(loss_rate(torch, pk, prec, steps=args.steps, warmup=1))
+    elif args.workload == "masked":
+        out.update(masked_field_rate(torch, pk, prec, sweeps=args.steps, warmup=1))
+    elif args.workload == "tiny":
+        out["sequential"] = pie_tiny_rate(torch, pk, 1, 0, sweeps=args.steps, warmup=1)
+        out["batched"] = pie_tiny_rate(torch, pk, 64, 1, sweeps=args.steps, warmup=1)
     if args.copy_calibration:
         copy_calibration(torch, out)
     print(json.dumps(out), flush=True)
