@@ -126,6 +126,7 @@ __global__ __launch_bounds__(fft_threads<G>()) void k_pie_fft(PieArgs a, int c0)
   bool valid;
   const int j = fft_pos_index(a.order, a.J, c0, q, &valid);
   const int2 ps = a.pos[j];
+  [[maybe_unused]] const size_t dbase = dpsi_base(a, q, valid ? ps.y : a.bb_c0);
   // exit wave psi = P * O[window] and the row pass A
   float mp = 0.f, mo = 0.f;
   for (int it = threadIdx.x; it < N * G::R2; it += blockDim.x) {
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(fft_threads<G>()) void k_pie_fft(PieArgs a, int c0)
           a.P[pi] = make_float2(p.x + sp * vp.x, p.y + sp * vp.y);
         }
       } else {
-        a.dpsi[(size_t)q * N * N + (size_t)row * N + col] = valid ? d : make_float2(0.f, 0.f);
+        a.dpsi[dbase + (size_t)row * a.dstride + col] = valid ? d : make_float2(0.f, 0.f);
       }
     }
   }

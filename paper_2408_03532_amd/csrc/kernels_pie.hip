@@ -18,9 +18,13 @@
 //                   list that belong to the chunk contribute conj(P) dpsi_j
 //                   and |P|^2 (FP64); the plain step is applied at once, the
 //                   overlap-normalised one is stored with per-tile maxima.
-//   k_pie_reduce_max, k_pie_apply   maxima and the normalised updates.
+//                   The gathers combine their maxima of D and E with
+//                   integer atomic maxima (per chunk parity).
+//   k_pie_apply     the normalised updates.
 // Per sweep: k_pie_begin (object copy, ranks, clears) and the statistics
-// pair k_pie_stats_part / k_pie_stats_final (fixed-order sums).
+// pair k_pie_stats_part / k_pie_stats_final (fixed-order sums); for one
+// overlap-normalised chunk without probe step k_pie_apply covers the whole
+// object and k_pie_stats_final alone follows.
 #include "internal.hpp"
 #include "pie.hpp"
 
@@ -75,6 +79,15 @@ __device__ __forceinline__ void pixel_stats(float2 ov, float2 nv, double& d2, do
   bad += (isfinite(nv.x) && isfinite(nv.y)) ? 0.0 : 1.0;
 }
 
+// max over the workgroup of non-negative doubles into *dst, whose bit
+// patterns order as unsigned integers: an integer atomic maximum, exact and
+// the same in any order (skipped when *dst is already as large).
+__device__ __forceinline__ void atomic_max_nonneg(double* dst, double v) {
+  unsigned long long* bits = reinterpret_cast<unsigned long long*>(dst);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  if (v > 0.0 && __hip_atomic_load(bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) atomicMax(bits, b);
+}
+
 __device__ __forceinline__ double block_max(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -86,7 +99,7 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 
 // Per probe pixel: numP = sum_q conj(O_j) dpsi_q, E = sum_q |O_j|^2 over the
 // chunk (O as at the chunk start).  Stores both and per-block maxima of E.
-__global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int cnt) {
+__global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int cnt, int par) {
   __shared__ double sh[4];
   const size_t nn = (size_t)a.n * a.n;
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,7 +126,7 @@ __global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int
         ov[u] = dv[u] = make_float2(0.f, 0.f);
         if (valid) {
           ov[u] = a.O[(size_t)(ps.x + k1) * a.W + ps.y + k2];
-          dv[u] = a.dpsi[(size_t)q * nn + k];
+          dv[u] = a.dpsi[dpsi_base(a, q, ps.y) + (size_t)k1 * a.dstride + k2];
         }
       }
 #pragma unroll
@@ -130,26 +143,20 @@ __global__ __launch_bounds__(256) void k_pie_probe_gather(PieArgs a, int c0, int
   }
   if (a.norm) {
     const double mx = block_max(e, sh);
-    if (threadIdx.x == 0) a.maxpart[a.tiles_x * a.tiles_y + blockIdx.x] = mx;
+    if (threadIdx.x == 0) atomic_max_nonneg(&a.maxes[2 * par + 1], mx);
   }
 }
 
 // Per 16 x 16 object tile of the bounding box: sum over the chunk's positions
 // in the tile's cover list.  norm 0: O += beta numO at once; norm 1: store
 // numO and D with the tile's maximum of D.
-__global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, int cnt) {
+__global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, int cnt, int par) {
   __shared__ double sh[4];
   const int tile = blockIdx.x;
   const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
   const int py = a.bb_r0 + ty * 16 + (threadIdx.x >> 4);
   const int px = a.bb_c0 + tx * 16 + (threadIdx.x & 15);
   const bool inside = (py < a.bb_r0 + a.bb_h) && (px < a.bb_c0 + a.bb_w);
-  const size_t nn = (size_t)a.n * a.n;
-  if (a.norm && tile == 0 && threadIdx.x == 0) {
-    // the maxima that k_pie_reduce_max collects next start from zero
-    a.maxes[0] = 0.0;
-    a.maxes[1] = 0.0;
-  }
   float2 acc = make_float2(0.f, 0.f);
   double D = 0.0;
   const int e0 = a.tile_ptr[tile], e1 = a.tile_ptr[tile + 1];
@@ -179,9 +186,8 @@ __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, in
       ok[u] = inside && qv[u] >= 0 && dy >= 0 && dy < a.n && dx >= 0 && dx < a.n;
       pv[u] = dv[u] = make_float2(0.f, 0.f);
       if (ok[u]) {
-        const size_t k = (size_t)dy * a.n + dx;
-        pv[u] = a.P[k];
-        dv[u] = a.dpsi[(size_t)qv[u] * nn + k];
+        pv[u] = a.P[(size_t)dy * a.n + dx];
+        dv[u] = a.dpsi[dpsi_base(a, qv[u], cv[u].y) + (size_t)dy * a.dstride + dx];
       }
     }
 #pragma unroll
@@ -218,59 +224,93 @@ __global__ __launch_bounds__(256) void k_pie_object_gather(PieArgs a, int c0, in
     a.D[o] = D;
   }
   const double mx = block_max(inside ? D : 0.0, sh);
-  if (threadIdx.x == 0) a.maxpart[tile] = mx;
+  if (threadIdx.x == 0) atomic_max_nonneg(&a.maxes[2 * par], mx);
 }
 
-// maxes[0] = max D over the tile maxima, maxes[1] = max E over the probe
-// blocks (both cleared by k_pie_object_gather).  The maxima are of
-// non-negative doubles, whose bit patterns order as unsigned integers, so
-// the blocks combine them with integer atomic maxima: exact, and the same
-// in any order.
-__global__ __launch_bounds__(256) void k_pie_reduce_max(PieArgs a, int nprobe_blocks) {
-  __shared__ double sh[4];
-  const int ntiles = a.tiles_x * a.tiles_y;
-  double mD = 0.0, mE = 0.0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
-    mD = fmax(mD, a.maxpart[t]);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nprobe_blocks; t += gridDim.x * blockDim.x)
-    mE = fmax(mE, a.maxpart[ntiles + t]);
-  mD = block_max(mD, sh);
+// stats = {Phi, ||dO||^2, ||O||^2, non-finite}: the objective parts, `nred`
+// statistics partials at red and `nfused` at fred, added in a fixed order by
+// one workgroup.
+__device__ void stats_sum(const PieArgs& a, int nred, int nfused) {
+  __shared__ double sh[4][16];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const size_t np = (size_t)a.J * 4;
+  for (size_t t = threadIdx.x; t < np; t += blockDim.x) v[0] += a.phi_part[t];
+  auto parts = [&](const double* src, int nb) {
+    // four partials per thread in flight, added in block order
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * blockDim.x) {
+      double t[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u * blockDim.x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[u][c] = b < nb ? src[(size_t)b * 3 + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c + 1] += t[u][c];
+    }
+  };
+  parts(a.red, nred);
+  parts(a.fred, nfused);
+  for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 4; ++c) sh[c][w] = v[c];
   __syncthreads();
-  mE = block_max(mE, sh);
   if (threadIdx.x == 0) {
-    unsigned long long* bits = reinterpret_cast<unsigned long long*>(a.maxes);
-    if (mD > 0.0) atomicMax(&bits[0], (unsigned long long)__double_as_longlong(mD));
-    if (mE > 0.0) atomicMax(&bits[1], (unsigned long long)__double_as_longlong(mE));
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nw; ++k)
+      for (int c = 0; c < 4; ++c) t[c] += sh[c][k];
+    a.stats[0] = t[0] / ((double)a.J * a.period * a.period);
+    a.stats[1] = t[1];
+    a.stats[2] = t[2];
+    a.stats[3] = t[3];
   }
 }
 
-// Normalised object update over the bounding box and the probe update.
-__global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part) {
+// Normalised object update over the bounding box and the probe update of
+// one chunk, with the maxima of the chunk's parity `par` (the other pair is
+// cleared for the next chunk).  fold_stats (one chunk, no probe step): the
+// object part runs over the whole object, outside the box only summing the
+// statistics, so that no statistics pass over the object follows.
+__global__ __launch_bounds__(256) void k_pie_apply(PieArgs a, int object_part, int par) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    a.maxes[2 * (par ^ 1)] = 0.0;
+    a.maxes[2 * (par ^ 1) + 1] = 0.0;
+  }
   if (object_part) {
-    const double regO = a.alpha * a.maxes[0];
+    const double regO = a.alpha * a.maxes[2 * par];
     double d2 = 0.0, o2 = 0.0, bad = 0.0;
-    // rows of the bounding box over blockIdx.y, columns over blockIdx.x
-    for (int rr = blockIdx.y; rr < a.bb_h; rr += gridDim.y)
-    for (int cc = blockIdx.x * blockDim.x + threadIdx.x; cc < a.bb_w; cc += gridDim.x * blockDim.x) {
-      const size_t o = (size_t)(a.bb_r0 + rr) * a.W + a.bb_c0 + cc;
-      const double d = a.D[o];
-      if (d > 0.0) {
-        const float sc = (float)((double)a.beta / (d + regO));
-        const float2 num = a.numO[o];
-        const float2 ov = a.O[o];
-        const float2 nv = make_float2(ov.x + sc * num.x, ov.y + sc * num.y);
-        a.O[o] = nv;
-        if (a.fuse_stats) pixel_stats(ov, nv, d2, o2, bad);
-      } else if (a.fuse_stats) {
-        const float2 ov = a.O[o];
-        pixel_stats(ov, ov, d2, o2, bad);
+    const bool fold = a.fold_stats;
+    const int r0 = fold ? 0 : a.bb_r0, c0 = fold ? 0 : a.bb_c0;
+    const int hh = fold ? a.H : a.bb_h, ww = fold ? a.W : a.bb_w;
+    // rows over blockIdx.y, columns over blockIdx.x
+    for (int rr = blockIdx.y; rr < hh; rr += gridDim.y) {
+      const int y = r0 + rr;
+      const bool in_rows = y >= a.bb_r0 && y < a.bb_r0 + a.bb_h;
+      for (int cc = blockIdx.x * blockDim.x + threadIdx.x; cc < ww; cc += gridDim.x * blockDim.x) {
+        const int x = c0 + cc;
+        const size_t o = (size_t)y * a.W + x;
+        const double d = (in_rows && x >= a.bb_c0 && x < a.bb_c0 + a.bb_w) ? a.D[o] : 0.0;
+        if (d > 0.0) {
+          const float sc = (float)((double)a.beta / (d + regO));
+          const float2 num = a.numO[o];
+          const float2 ov = a.O[o];
+          const float2 nv = make_float2(ov.x + sc * num.x, ov.y + sc * num.y);
+          a.O[o] = nv;
+          if (a.fuse_stats) pixel_stats(ov, nv, d2, o2, bad);
+        } else if (a.fuse_stats) {
+          const float2 ov = a.O[o];
+          pixel_stats(ov, ov, d2, o2, bad);
+        }
       }
     }
     if (a.fuse_stats) block_sum3(d2, o2, bad, a.fred + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 3);
   }
   if (a.probe_step) {
     const size_t nn = (size_t)a.n * a.n;
-    const double regP = a.alpha * a.maxes[1];
+    const double regP = a.alpha * a.maxes[2 * par + 1];
     const size_t nthreads = (size_t)gridDim.x * gridDim.y * blockDim.x;
     const size_t t0 = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
     for (size_t t = t0; t < nn; t += nthreads) {
@@ -302,6 +342,8 @@ __global__ __launch_bounds__(256) void k_pie_begin(PieArgs a) {
     a.winmax[2 * t + 1] = 0u;
   }
   for (size_t t = t0; t < (size_t)a.J * 4; t += stride) a.phi_part[t] = 0.0;
+  if (t0 == 0)
+    for (int k = 0; k < 4; ++k) a.maxes[k] = 0.0;
 }
 
 // rank[order[t]] = t for the entries of the order inside [0, J); a position
@@ -320,17 +362,21 @@ __global__ __launch_bounds__(256) void k_pie_stats_part(PieArgs a) {
   __shared__ double sh[3][4];
   const size_t total = (size_t)a.H * a.W;
   double d2 = 0.0, o2 = 0.0, bad = 0.0;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    if (a.fuse_stats) {
-      // the box was summed by the update; outside it the object is unchanged
-      const int y = (int)(t / a.W) - a.bb_r0, x = (int)(t % a.W) - a.bb_c0;
-      if (y >= 0 && y < a.bb_h && x >= 0 && x < a.bb_w) continue;
-      const float2 z = a.O[t];
-      pixel_stats(z, z, d2, o2, bad);
-      continue;
+  if (a.fuse_stats) {
+    // the box was summed by the update; outside it the object is unchanged:
+    // rows over workgroups, and in the box's rows only the columns beside it
+    for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
+      const float2* row = a.O + (size_t)y * a.W;
+      const bool in_rows = y >= a.bb_r0 && y < a.bb_r0 + a.bb_h;
+      const int xa = in_rows ? a.bb_c0 : a.W, xb = in_rows ? a.bb_c0 + a.bb_w : a.W;
+      for (int x = threadIdx.x; x < xa; x += blockDim.x) pixel_stats(row[x], row[x], d2, o2, bad);
+      for (int x = xb + threadIdx.x; x < a.W; x += blockDim.x) pixel_stats(row[x], row[x], d2, o2, bad);
     }
-    const float2 o = a.O[t], z = a.O0[t];
-    pixel_stats(z, o, d2, o2, bad);
+  } else {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+      const float2 o = a.O[t], z = a.O0[t];
+      pixel_stats(z, o, d2, o2, bad);
+    }
   }
   if (a.probe_step) {
     const size_t nn = (size_t)a.n * a.n;
@@ -356,30 +402,9 @@ __global__ __launch_bounds__(256) void k_pie_stats_part(PieArgs a) {
   }
 }
 
-// stats = {Phi, ||dO||^2, ||O||^2, non-finite}: one wave, fixed order.
+// stats after the statistics partials (kStatBlocks at red, nfused at fred).
 __global__ __launch_bounds__(1024) void k_pie_stats_final(PieArgs a, int nblocks, int nfused) {
-  __shared__ double sh[4][16];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const size_t np = (size_t)a.J * 4;
-  for (size_t t = threadIdx.x; t < np; t += blockDim.x) v[0] += a.phi_part[t];
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-    for (int c = 0; c < 3; ++c) v[c + 1] += a.red[(size_t)b * 3 + c];
-  for (int b = threadIdx.x; b < nfused; b += blockDim.x)
-    for (int c = 0; c < 3; ++c) v[c + 1] += a.fred[(size_t)b * 3 + c];
-  for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
-  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-    for (int c = 0; c < 4; ++c) sh[c][w] = v[c];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < nw; ++k)
-      for (int c = 0; c < 4; ++c) s[c] += sh[c][k];
-    a.stats[0] = s[0] / ((double)a.J * a.period * a.period);
-    a.stats[1] = s[1];
-    a.stats[2] = s[2];
-    a.stats[3] = s[3];
-  }
+  stats_sum(a, nblocks, nfused);
 }
 
 // amp[j][c1][c2] = sqrt(I[j][s + c1][s + c2]), s = floor(n/2) - floor(m/2)
@@ -463,8 +488,10 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
   obj_pass.probe_step = 0;
   probe_pass.probe_pass = 1;
   int nfused = 0;  // statistics partials written by the update (single-chunk sweeps)
+  bool stats_done = false;
   for (int c0 = 0; c0 < a.J; c0 += batch) {
     const int cnt = (a.J - c0 < batch) ? a.J - c0 : batch;
+    const int par = (c0 / batch) & 1;  // maxima pair of this chunk
     hipError_t e;
     if (a.probe_literal) {
       if ((e = run_chunk(obj_pass, c0, cnt)) != hipSuccess) return e;
@@ -473,33 +500,29 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
       return e;
     }
     if (cnt == 1) continue;  // updated in place
-    if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt);
-    hipLaunchKernelGGL(k_pie_object_gather, dim3(ntiles), dim3(256), 0, st, a, c0, cnt);
+    if (a.probe_step) hipLaunchKernelGGL(k_pie_probe_gather, dim3(pblocks), dim3(256), 0, st, a, c0, cnt, par);
+    hipLaunchKernelGGL(k_pie_object_gather, dim3(ntiles), dim3(256), 0, st, a, c0, cnt, par);
     if (a.fuse_stats && !a.norm) nfused = ntiles;
-    if (a.norm) {
-      const int items = ntiles > pblocks ? ntiles : pblocks;
-      int rb = (items + 255) / 256;
-      if (rb > 1024) rb = 1024;
-      hipLaunchKernelGGL(k_pie_reduce_max, dim3(rb), dim3(256), 0, st, a, a.probe_step ? pblocks : 0);
-    }
     if (a.norm || a.probe_step) {
-      // object part: columns of the bounding box over x, rows over y; the
-      // probe part runs over the flattened grid
+      // object part: columns (of the bounding box, or of the whole object
+      // when the statistics are folded in) over x, rows over y; the probe
+      // part runs over the flattened grid
       int gx = 1, gy = 1;
       if (a.norm) {
-        gx = (a.bb_w + 255) / 256;
-        gy = a.bb_h;
+        gx = ((a.fold_stats ? a.W : a.bb_w) + 255) / 256;
+        gy = a.fold_stats ? a.H : a.bb_h;
         if (gx > 64) gx = 64;
         if (gy > 4096 / gx) gy = 4096 / gx;
       }
       const int pb = a.probe_step ? ew_blocks((size_t)a.n * a.n) : 1;
       if (gx * gy < pb) gy = (pb + gx - 1) / gx;
-      hipLaunchKernelGGL(k_pie_apply, dim3(gx, gy), dim3(256), 0, st, a, a.norm);
+      hipLaunchKernelGGL(k_pie_apply, dim3(gx, gy), dim3(256), 0, st, a, a.norm, par);
       if (a.fuse_stats && a.norm) nfused = gx * gy;
+      stats_done = a.fold_stats;
     }
   }
-  hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, kStatBlocks, nfused);
+  if (!stats_done) hipLaunchKernelGGL(k_pie_stats_part, dim3(kStatBlocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_pie_stats_final, dim3(1), dim3(1024), 0, st, a, stats_done ? 0 : kStatBlocks, nfused);
   return hipGetLastError();
 }
 

@@ -48,7 +48,8 @@ struct PieArgs {
   float2* part;     // [batch][splits][m][m] partial spectra (row groups split over workgroups)
   int splits;       // workgroups per position in the forward (1: whole window in one)
   int num_cu;       // compute units of the device
-  float2* dpsi;     // [batch][n][n] corrections (chunks of more than one position)
+  float2* dpsi;     // [batch][n][dstride] corrections (chunks of more than one position), see dpsi_base
+  int dstride;      // row stride of a stored correction (complex elements, a multiple of 16)
   double* phi_part; // [J][4]
   int32_t* rank;    // [J] place of each position in the sweep order
   unsigned* winmax; // [J][2] float bits of max |P|^2, max |O_j|^2 over the window (single-position chunks)
@@ -57,8 +58,7 @@ struct PieArgs {
   double* D;        // [H][W]
   float2* numP;     // [n][n] (probe step, multi-position chunks)
   double* E;        // [n][n]
-  double* maxpart;  // [tiles + probe blocks] per-block maxima of D and E
-  double* maxes;    // [2]
+  double* maxes;    // [2][2] max D, max E of even / odd chunks (combined by integer atomic maxima)
   double* red;      // [kStatBlocks][3] statistics partials
   double* stats;    // [4]
   // single-chunk sweeps: the kernels that update the object also sum
@@ -66,19 +66,20 @@ struct PieArgs {
   // fred[block][3], so no object copy is taken at the sweep start and the
   // statistics pass reads only the pixels outside the box
   int fuse_stats;
+  int fold_stats;   // ... and, overlap-normalised without probe step, k_pie_apply covers the whole object
   double* fred;     // [kFusedRedBlocks or tiles][3]
 };
 
 constexpr int kStatBlocks = 2048;
 constexpr int kFusedRedBlocks = 4096 + 64;  // the most workgroups k_pie_apply launches
-constexpr int32_t kRankAbsent = 0x7fffffff;
+constexpr int32_t kRankAbsent = 0x7fffffff;  // rank of a position the sweep order leaves out
 // Sequential sweeps (chunks of one position) of windows up to kSeqMaxNb
 // tiles of 16 per axis and up to 32 kept coefficients run in one
 // persistent workgroup.
 constexpr int kSeqMaxNb = 4;
 // LDS a sequential sweep may hold (object box, probe, residual, tables).
 constexpr size_t kSeqLdsBytes = 144 * 1024;
-constexpr size_t kSeqLdsMaxObject = 1 << 16;  // object pixels  // rank of a position the sweep order leaves out
+constexpr size_t kSeqLdsMaxObject = 1 << 16;  // object pixels
 
 // Forward work split of the dense sweep for MT = ceil(m/16) tiles per axis:
 // CT column tiles per wave, WC column groups, WR row groups per workgroup.
@@ -148,6 +149,8 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st);
 hipError_t launch_crop_amp(const float* I, int J, int n, int m, float* amp, hipStream_t st);
 hipError_t launch_pie_fft_chunk(const PieArgs& a, int c0, int cnt, hipStream_t st);
 int pie_probe_blocks(int n);
+// Row stride of a stored correction: n columns after a shift of up to 15.
+inline int dpsi_stride(int n) { return (n + 30) / 16 * 16; }
 
 #ifdef __HIPCC__
 // Position of entry q of the chunk starting at c0.  An order entry outside
@@ -160,6 +163,14 @@ __device__ __forceinline__ int pos_index(const int32_t* __restrict__ order, int 
   return ok ? j : 0;
 }
 
+// Stored correction of chunk entry q at window column c: row k1, column k2
+// at dpsi_base + k1 * dstride + k2.  The row is shifted right by
+// (c - bb_c0) mod 16 so that each 16-pixel row segment of an object tile
+// (tiles start at bb_c0 + 16 t) begins on a 128-byte line; the object gather
+// then reads whole lines.
+__host__ __device__ __forceinline__ size_t dpsi_base(const PieArgs& a, int q, int c) {
+  return (size_t)q * a.n * a.dstride + ((c - a.bb_c0) & 15);
+}
 // psi[k1][k2] = P[k1][k2] * O[r + k1][c + k2]; zero outside the n x n patch.
 // The engines prefetch the raw probe and object values (load_raw) and form
 // the products (combine) just before the block's MFMA products.

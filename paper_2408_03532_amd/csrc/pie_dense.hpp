@@ -264,10 +264,10 @@ struct UpdateSink {
   }
 };
 
-// Larger chunks: store dpsi = X / n^2.
+// Larger chunks: store dpsi = X / n^2 (rows of `stride`, from dpsi_base).
 struct DeltaSink {
   float2* __restrict__ out;
-  int n;
+  int n, stride;
   float inv;
   template <bool TR>
   __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
@@ -275,7 +275,7 @@ struct DeltaSink {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int2 rc = tile_rc<TR>(k1t, k2t, i, lane);
-      if (rc.x < n && rc.y < n) out[(size_t)rc.x * n + rc.y] = make_float2(xre[i] * inv, xim[i] * inv);
+      if (rc.x < n && rc.y < n) out[(size_t)rc.x * stride + rc.y] = make_float2(xre[i] * inv, xim[i] * inv);
     }
   }
 };
@@ -307,7 +307,8 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
         adj_engine<PR, MT>(src, a.nb, T, kt2, sink);
     }
   } else {
-    DeltaSink sink{a.dpsi + (size_t)q * a.n * a.n, a.n, a.inv_n2};
+    const int c = valid ? a.pos[j].y : a.bb_c0;
+    DeltaSink sink{a.dpsi + dpsi_base(a, q, c), a.n, a.dstride, a.inv_n2};
     if constexpr (K2 > 1) {
       for (int gi = blockIdx.y * nw + w; gi * K2 < a.nb; gi += gridDim.y * nw)
         adj_tiles_f32<MT, K2>(src, a.nb, T, gi * K2, sink);
@@ -695,9 +696,9 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a
   // {Phi, ||O_after - O_before||^2, ||O_before||^2, non-finite}
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = tid; i < a.J * 4; i += nt) v[0] += a.phi_part[i];
-  const size_t total = (size_t)a.H * a.W;
-  for (size_t i = tid; i < total; i += nt) {
-    const int y = (int)(i / a.W), x = (int)(i % a.W);
+  const int total = a.H * a.W;  // at most kSeqLdsMaxObject
+  for (int i = tid; i < total; i += nt) {
+    const int y = i / a.W, x = i - y * a.W;
     const float2 z = a.O[i];
     float2 o = z;
     const int yy = y - a.bb_r0, xx = x - a.bb_c0;

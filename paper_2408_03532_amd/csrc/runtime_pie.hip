@@ -24,7 +24,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace carve-up of one sweep; sizes in bytes, offsets 256-aligned.
 struct PieLayout {
-  size_t R, part, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxpart, maxes, red, stats, fred, total;
+  size_t R, part, dpsi, phi, rank, winmax, O0, numO, D, numP, E, maxes, red, stats, fred, total;
   int fuse;
   int splits;
 };
@@ -50,20 +50,19 @@ PieLayout pie_layout(const pie_scan_s* s, int batch, int norm, int probe_step) {
                               p->prec == PFTPIE_FP32 && p->n % 16 == 0);
   }
   L.part = L.splits > 1 ? take((size_t)batch * L.splits * p->m * p->m * 8) : SIZE_MAX;
-  L.dpsi = multi ? take((size_t)batch * nn * 8) : SIZE_MAX;
+  L.dpsi = multi ? take((size_t)batch * p->n * dpsi_stride(p->n) * 8) : SIZE_MAX;
   L.phi = take((size_t)s->J * 4 * 8);
   L.rank = take((size_t)s->J * 4);
   L.winmax = take((size_t)s->J * 8);
   // one chunk of several positions: statistics fused into the update, no
-  // object copy
-  L.fuse = multi && batch >= s->J;
+  // object copy (one position alone is updated in place, with the copy)
+  L.fuse = multi && batch >= s->J && s->J > 1;
   L.O0 = L.fuse ? SIZE_MAX : take(obj * 8);
   L.numO = (multi && norm) ? take(obj * 8) : SIZE_MAX;
   L.D = (multi && norm) ? take(obj * 8) : SIZE_MAX;
   L.numP = (multi && probe_step) ? take(nn * 8) : SIZE_MAX;
   L.E = (multi && probe_step && norm) ? take(nn * 8) : SIZE_MAX;
-  L.maxpart = take(((size_t)s->tiles_x * s->tiles_y + pie_probe_blocks(p->n)) * 8);
-  L.maxes = take(16);
+  L.maxes = take(32);
   L.red = take((size_t)kStatBlocks * 3 * 8);
   L.stats = take(32);
   L.fred = L.fuse ? take((size_t)std::max<size_t>((size_t)s->tiles_x * s->tiles_y, kFusedRedBlocks) * 3 * 8) : SIZE_MAX;
@@ -183,6 +182,7 @@ pftpie_status sweep(pie_scan scan, void* object, void* probe, const float* amp, 
   a.splits = L.splits;
   a.num_cu = pl->num_cu;
   a.dpsi = static_cast<float2*>(at(L.dpsi));
+  a.dstride = dpsi_stride(pl->n);
   a.phi_part = static_cast<double*>(at(L.phi));
   a.rank = static_cast<int32_t*>(at(L.rank));
   a.winmax = static_cast<unsigned*>(at(L.winmax));
@@ -191,11 +191,11 @@ pftpie_status sweep(pie_scan scan, void* object, void* probe, const float* amp, 
   a.D = static_cast<double*>(at(L.D));
   a.numP = static_cast<float2*>(at(L.numP));
   a.E = static_cast<double*>(at(L.E));
-  a.maxpart = static_cast<double*>(at(L.maxpart));
   a.maxes = static_cast<double*>(at(L.maxes));
   a.red = static_cast<double*>(at(L.red));
   a.stats = stats_dev ? stats_dev : static_cast<double*>(at(L.stats));
   a.fuse_stats = L.fuse;
+  a.fold_stats = L.fuse && p->norm && !probe_step;
   a.fred = static_cast<double*>(at(L.fred));
   hipError_t e = launch_pie_sweep(a, batch, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PFTPIE_OK : hip_fail(e, (name + ": launch").c_str());
