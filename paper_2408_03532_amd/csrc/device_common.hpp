@@ -54,6 +54,14 @@ __device__ __forceinline__ c4 load_tw(const float4* __restrict__ blk, int lane) 
   return r;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads still in
+// flight (prefetches) are not waited for, unlike __syncthreads.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;

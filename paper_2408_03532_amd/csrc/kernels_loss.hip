@@ -24,7 +24,7 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(Loss
   const int w = threadIdx.x >> 6;
   const int c2t0 = w * CT;
   const int2 ps = a.pos[j];
-  GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
+  GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y, a.n};
   f32x4 Yre[MT][CT], Yim[MT][CT];
   fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim);
   const int lane = lane_id();

@@ -99,7 +99,7 @@ struct PlainSrc {
 // to 8 tiles per wave, whose three accumulator sets fit the registers).
 template <int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
-                                         f32x4 (&Yim)[MT][CT], int strip0, int sstep) {
+                                         f32x4 (&Yim)[MT][CT], int strip0, int sstep, int kb0 = 0, int kbs = 1) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
   // Yre accumulates k1, Yim k3, Y2 k2 of the stage-2 products
@@ -147,17 +147,21 @@ __device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab
     };
     Raw a0, a1;
     c4 f0[CT], f1[CT];
-    fetch(0, a0, f0);
-    int kb = 0;
-    for (; kb + 1 < NB; kb += 2) {
-      fetch(kb + 1, a1, f1);
-      __builtin_amdgcn_sched_barrier(0);
-      stage1(a0, f0);
-      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
-      __builtin_amdgcn_sched_barrier(0);
-      stage1(a1, f1);
+    if (kb0 < NB) {
+      // column blocks kb0, kb0 + kbs, ... (all of them unless several waves
+      // share the strip's sum)
+      fetch(kb0, a0, f0);
+      int kb = kb0;
+      for (; kb + kbs < NB; kb += 2 * kbs) {
+        fetch(kb + kbs, a1, f1);
+        __builtin_amdgcn_sched_barrier(0);
+        stage1(a0, f0);
+        fetch(kb + 2 * kbs < NB ? kb + 2 * kbs : kb + kbs, a0, f0);
+        __builtin_amdgcn_sched_barrier(0);
+        stage1(a1, f1);
+      }
+      if (kb < NB) stage1(a0, f0);
     }
-    if (kb < NB) stage1(a0, f0);
     // T strip = a + ib with a = k1 - k2, b = k1 + k3; stage 2 takes T as the
     // data side: a in T1, a + b in T2, b - a in T3
 #pragma unroll
@@ -197,7 +201,7 @@ __device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab
 // formed in a register), for wider output blocks.
 template <int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
-                                              f32x4 (&Yim)[MT][CT], int strip0, int sstep) {
+                                              f32x4 (&Yim)[MT][CT], int strip0, int sstep, int kb0 = 0, int kbs = 1) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -240,17 +244,21 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
     };
     Raw a0, a1;
     c4 f0[CT], f1[CT];
-    fetch(0, a0, f0);
-    int kb = 0;
-    for (; kb + 1 < NB; kb += 2) {
-      fetch(kb + 1, a1, f1);
-      __builtin_amdgcn_sched_barrier(0);
-      stage1(a0, f0);
-      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
-      __builtin_amdgcn_sched_barrier(0);
-      stage1(a1, f1);
+    if (kb0 < NB) {
+      // column blocks kb0, kb0 + kbs, ... (all of them unless several waves
+      // share the strip's sum)
+      fetch(kb0, a0, f0);
+      int kb = kb0;
+      for (; kb + kbs < NB; kb += 2 * kbs) {
+        fetch(kb + kbs, a1, f1);
+        __builtin_amdgcn_sched_barrier(0);
+        stage1(a0, f0);
+        fetch(kb + 2 * kbs < NB ? kb + 2 * kbs : kb + kbs, a0, f0);
+        __builtin_amdgcn_sched_barrier(0);
+        stage1(a1, f1);
+      }
+      if (kb < NB) stage1(a0, f0);
     }
-    if (kb < NB) stage1(a0, f0);
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
       c4 fb = FA.f32((size_t)c1t * NB + strip, lane);
@@ -275,13 +283,16 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
 // Forward engine.  NB = ceil(n/16) row strips / column blocks.  FA holds
 // ctiles x NB blocks.  c2t0: first column tile this wave owns; the wave
 // runs strips strip0, strip0 + sstep, ...
+// With kbs > 1 the wave sums column blocks kb0, kb0 + kbs, ... only: kbs
+// waves then hold partial results whose sum is the transform.
 template <int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
-                                         f32x4 (&Yim)[MT][CT], int strip0 = 0, int sstep = 1) {
+                                         f32x4 (&Yim)[MT][CT], int strip0 = 0, int sstep = 1, int kb0 = 0,
+                                         int kbs = 1) {
   if constexpr (MT * CT <= 8)
-    fwd_wave_gauss<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
+    fwd_wave_gauss<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, kb0, kbs);
   else
-    fwd_wave_four<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);
+    fwd_wave_four<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, kb0, kbs);
 }
 
 // Forward engine for long windows whose twiddle table does not stay in the
@@ -389,7 +400,7 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
 // four products per complex product.
 template <int MT, int K1, class Sink, class Tab>
 __device__ __forceinline__ void adj_stage2_four(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,
-                                                int kt2, Sink& sink) {
+                                                int kt2, Sink& sink, int k1_first = 0, int k1_step = 1) {
   const int lane = lane_id();
   // stage 2: X[k1][k2] = sum_c1 conj(F[c1][k1]) S[c1][k2], K1 row tiles at a
   // time; the twiddle blocks of the next step are fetched while the current
@@ -402,9 +413,10 @@ __device__ __forceinline__ void adj_stage2_four(const f32x4 (&Sre)[MT], const f3
     }
   };
   c4 fb[2][K1];
-  fetch2(0, 0, fb[0]);
-  for (int k1t = 0; k1t < NB; k1t += K1) {
-    const int k1n = (k1t + K1 < NB) ? k1t + K1 : k1t;
+  const int k1s = K1 * k1_step;
+  fetch2(K1 * k1_first, 0, fb[0]);
+  for (int k1t = K1 * k1_first; k1t < NB; k1t += k1s) {
+    const int k1n = (k1t + k1s < NB) ? k1t + k1s : k1t;
     f32x4 Xre[K1], Xim[K1];
 #pragma unroll
     for (int u = 0; u < K1; ++u) {
@@ -448,7 +460,8 @@ __device__ __forceinline__ void adj_stage2_four(const f32x4 (&Sre)[MT], const f3
 // (k2' = -k2 of the Gauss form).  a + b and b - a are formed once per tile.
 template <int MT, int K1, class Sink, class Tab>
 __device__ __forceinline__ void adj_stage2_gauss(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB,
-                                                 const Tab& FT, int kt2, Sink& sink) {
+                                                 const Tab& FT, int kt2, Sink& sink, int k1_first = 0,
+                                                 int k1_step = 1) {
   const int lane = lane_id();
   f32x4 Ssum[MT], Sdif[MT];
 #pragma unroll
@@ -464,9 +477,10 @@ __device__ __forceinline__ void adj_stage2_gauss(const f32x4 (&Sre)[MT], const f
     }
   };
   c4 fb[2][K1];
-  fetch2(0, 0, fb[0]);
-  for (int k1t = 0; k1t < NB; k1t += K1) {
-    const int k1n = (k1t + K1 < NB) ? k1t + K1 : k1t;
+  const int k1s = K1 * k1_step;
+  fetch2(K1 * k1_first, 0, fb[0]);
+  for (int k1t = K1 * k1_first; k1t < NB; k1t += k1s) {
+    const int k1n = (k1t + k1s < NB) ? k1t + k1s : k1t;
     f32x4 X1[K1], X2[K1], X3[K1];
 #pragma unroll
     for (int u = 0; u < K1; ++u) {
@@ -501,20 +515,23 @@ __device__ __forceinline__ void adj_stage2_gauss(const f32x4 (&Sre)[MT], const f
 }
 
 // FP32 adjoint, stage 2 of column tile kt2 from the stage-1 accumulators S.
+// Row tiles k1_first * K1, (k1_first + k1_step) * K1, ... (K1 at a time) only
+// when several waves share the tile's rows.
 template <int MT, int K1, class Sink, class Tab>
 __device__ __forceinline__ void adj_stage2_f32(const f32x4 (&Sre)[MT], const f32x4 (&Sim)[MT], int NB, const Tab& FT,
-                                               int kt2, Sink& sink) {
+                                               int kt2, Sink& sink, int k1_first = 0, int k1_step = 1) {
   if constexpr (MT <= 4 && K1 <= 2)
-    adj_stage2_gauss<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
+    adj_stage2_gauss<MT, K1>(Sre, Sim, NB, FT, kt2, sink, k1_first, k1_step);
   else
-    adj_stage2_four<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
+    adj_stage2_four<MT, K1>(Sre, Sim, NB, FT, kt2, sink, k1_first, k1_step);
 }
 
 // Adjoint engine for one 16-column tile kt2 of X.  ysrc.load(row, col0)
 // returns Y[row][col0..col0+3] (zeros outside m x m).  FT holds NB x MT
 // blocks.  sink.put<false>(k1t, kt2, Xre, Xim) receives each finished tile.
 template <int MT, class YSrc, class Sink, class Tab, int K1 = 2>
-__device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Tab& FT, int kt2, Sink& sink) {
+__device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Tab& FT, int kt2, Sink& sink,
+                                              int k1_first = 0, int k1_step = 1) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
   f32x4 Sre[MT], Sim[MT];
@@ -562,7 +579,7 @@ __device__ __forceinline__ void adj_wave_tile(const YSrc& ysrc, int NB, const Ta
       stage1(f, y);
     }
   }
-  adj_stage2_f32<MT, K1>(Sre, Sim, NB, FT, kt2, sink);
+  adj_stage2_f32<MT, K1>(Sre, Sim, NB, FT, kt2, sink, k1_first, k1_step);
 }
 
 // FP32 adjoint for long windows: K2 neighbouring column tiles kt2_0 ..

@@ -184,10 +184,11 @@ struct GatherSrc {
   const float2* __restrict__ O;
   const float2* __restrict__ P;
   int W, n, r, c;
+  int ldp;  // row stride of P (n, or padded in LDS)
   __device__ __forceinline__ Raw load_raw(int row, int col0) const {
     Raw v;
     const float2* orow = O + (size_t)(r + row) * W + c + col0;
-    const float2* prow = P + (size_t)row * n + col0;
+    const float2* prow = P + (size_t)row * ldp + col0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int col = col0 + s;

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
   const int G = SPLIT ? (int)gridDim.y * WR : WR;
   f32x4 Yre[MT][CT], Yim[MT][CT];
   if constexpr (TRACK) {
-    GatherTrackSrc<EXACT> src{{a.O, a.P, a.W, a.n, ps.x, ps.y}, 0.f, 0.f};
+    GatherTrackSrc<EXACT> src{{a.O, a.P, a.W, a.n, ps.x, ps.y, a.n}, 0.f, 0.f};
     fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, g0, G);
     if (wc == 0) {
       const float mp = wave_max(src.mp), mo = wave_max(src.mo);
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(64 * WR * ((MT + CT - 1) / CT)) void k_pie_forward(
       }
     }
   } else {
-    GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y};
+    GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y, a.n};
     if constexpr (RS > 1)
       fwd_wave_rs<MT, CT, RS>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim, g0, G);
     else
@@ -224,6 +224,7 @@ struct UpdateSink {
   int n, W, r, c, norm, probe_step, valid, probe_pass;
   float inv, beta, gamma;
   double regP, regO;  // alpha * max |P|^2, alpha * max |O_j|^2
+  int ldp;            // row stride of P (n, or padded in LDS)
   template <bool TR>
   __device__ __forceinline__ void put(int k1t, int k2t, const f32x4& xre, const f32x4& xim) const {
     if (!valid) return;
@@ -234,7 +235,7 @@ struct UpdateSink {
       const int k1 = rc.x, k2 = rc.y;
       if (k1 < n && k2 < n) {
         const float2 d = make_float2(xre[i] * inv, xim[i] * inv);
-        const size_t pi = (size_t)k1 * n + k2;
+        const size_t pi = (size_t)k1 * ldp + k2;
         const size_t o = (size_t)(r + k1) * W + (c + k2);
         const float2 p = P[pi];
         const float2 ov = O[o];
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
       regO = a.alpha * (double)__uint_as_float(a.winmax[2 * j + 1]);
     }
     UpdateSink sink{a.O, a.P, a.n, a.W, ps.x, ps.y, a.norm, a.probe_step, (int)valid, a.probe_pass,
-                    a.inv_n2, a.beta, a.gamma, regP, regO};
+                    a.inv_n2, a.beta, a.gamma, regP, regO, a.n};
     if constexpr (K2 > 1) {
       for (int gi = blockIdx.y * nw + w; gi * K2 < a.nb; gi += gridDim.y * nw)
         adj_tiles_f32<MT, K2>(src, a.nb, T, gi * K2, sink);
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential(PieArgs a) {
       f32x4 Yre[MT][CT], Yim[MT][CT];
       if (fwd_wave) {
         if (track) {
-          GatherTrackSrc<EXACT> src{{b.O, b.P, b.W, b.n, ps.x, ps.y}, 0.f, 0.f};
+          GatherTrackSrc<EXACT> src{{b.O, b.P, b.W, b.n, ps.x, ps.y, b.n}, 0.f, 0.f};
           fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
           if (wc == 0) {
             const float mp = wave_max(src.mp), mo = wave_max(src.mo);
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential(PieArgs a) {
             }
           }
         } else {
-          GatherSrc<EXACT> src{b.O, b.P, b.W, b.n, ps.x, ps.y};
+          GatherSrc<EXACT> src{b.O, b.P, b.W, b.n, ps.x, ps.y, b.n};
           fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
         }
         if (WR > 1 && wr > 0) {
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential(PieArgs a) {
         regO = b.alpha * (double)__uint_as_float(b.winmax[2 * j + 1]);
       }
       UpdateSink sink{b.O, b.P, b.n, b.W, ps.x, ps.y, b.norm, b.probe_step, (int)valid, b.probe_pass,
-                      b.inv_n2, b.beta, b.gamma, regP, regO};
+                      b.inv_n2, b.beta, b.gamma, regP, regO, b.n};
       ResSrc rsrc{b.R, b.m};
       for (int kt2 = w; kt2 < b.nb; kt2 += kSeqWaves) adj_engine<PR, MT>(rsrc, b.nb, FT, kt2, sink);
       __syncthreads();
@@ -526,45 +527,85 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential(PieArgs a) {
 // there, and the end of the sweep computes the statistics (against the
 // object still in global memory) before writing the box back.  One launch
 // per sweep; used when these fit the compute unit's LDS.
+//
+// Without probe step a position changes the object only inside its own
+// window, so eq. (5) in sweep order gives the same result whenever every
+// pair of overlapping positions runs in sweep order.  TEAMS > 1: the sweep
+// is cut into dependency levels (a position's level is one more than the
+// highest level of the earlier positions whose windows overlap it, so the
+// positions of one level have disjoint windows) and TEAMS groups of
+// kSeqWaves waves take the positions of a level side by side.  Every pixel
+// then sees the same updates in the same order as in the one-by-one sweep.
 struct SeqLdsLayout {
-  size_t obj, probe, res, fa, ft, pos, jidx, total;
+  size_t obj, probe, res, fa, ft, pos, jidx, lvl, sched, lstart, rtab, total;
+  int ldo, ldp;  // row strides of the object box and the probe
 };
 
+// LDS row stride for rows of `w` complex values: rows read down a column
+// then start 8 banks apart (stride = 4 mod 32 complex values).
+__host__ __device__ inline int seq_lds_stride(int w) { return w + ((36 - w % 32) % 32); }
+
 __host__ __device__ inline SeqLdsLayout seq_lds_layout(int bb_h, int bb_w, int n, int m, int J, size_t fa_bytes,
-                                                         size_t ft_bytes) {
+                                                         size_t ft_bytes, int teams) {
   SeqLdsLayout L;
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  L.ldo = seq_lds_stride(bb_w);
+  L.ldp = seq_lds_stride(n);
   L.fa = 0;
   L.ft = up(fa_bytes);
   L.obj = L.ft + up(ft_bytes);
-  L.probe = L.obj + up((size_t)bb_h * bb_w * 8);
-  L.res = L.probe + up((size_t)n * n * 8);
-  L.pos = L.res + up((size_t)m * m * 8);
+  L.probe = L.obj + up((size_t)bb_h * L.ldo * 8);
+  L.res = L.probe + up((size_t)n * L.ldp * 8);
+  L.pos = L.res + (size_t)teams * up((size_t)m * m * 8);
   L.jidx = L.pos + up((size_t)J * 8);
-  L.total = L.jidx + up((size_t)J * 4);
+  // levels: each step's level, the steps in level order, where each level
+  // starts (J + 1), and each round's step per team (-1: none)
+  const size_t lv = teams > 1 ? up((size_t)J * 4) : 0;
+  L.lvl = L.jidx + up((size_t)J * 4);
+  L.sched = L.lvl + lv;
+  L.lstart = L.sched + lv;
+  L.rtab = L.lstart + (teams > 1 ? up((size_t)(J + 1) * 4) : 0);
+  L.total = L.rtab + (teams > 1 ? up((size_t)J * teams * 4) : 0);
   return L;
 }
 
-template <class PR, int MT, bool EXACT>
-__global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a, size_t fa_bytes, size_t ft_bytes) {
+constexpr int kSeqLevelMaxJ = 2048;  // positions for which the levels are worth finding (O(J^2 / 64) steps)
+
+template <class PR, int MT, bool EXACT, int TEAMS>
+__global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(PieArgs a, size_t fa_bytes,
+                                                                               size_t ft_bytes) {
   constexpr int CT = (MT <= 2) ? MT : 2;
   constexpr int WC = (MT + CT - 1) / CT;
   constexpr int WR = pie_wr<MT>();
-  static_assert(WR * WC <= kSeqWaves, "the forward's waves must fit the workgroup");
+  // FP32: the waves the row groups leave over split each strip's column
+  // blocks (KS partial sums per row group)
+  constexpr int KS = Orient<PR>::TR ? 1 : kSeqWaves / (WR * WC);
+  constexpr int NP = WR * KS;  // partial spectra per column group
+  constexpr int PART = (NP > 1 ? (NP - 1) * WC : 1) * MT * CT * 2 * 64;
+  static_assert(WR * WC <= kSeqWaves && KS >= 1, "the forward's waves must fit the team");
   extern __shared__ f32x4 dyn[];
-  __shared__ f32x4 part[(WR > 1 ? (WR - 1) * WC : 1) * MT * CT * 2 * 64];
-  __shared__ double red[kSeqWaves][4];
-  __shared__ unsigned wmx[2][2];  // per-position max |P|^2, max |O_j|^2 (double-buffered by position parity)
+  __shared__ f32x4 part[TEAMS][PART];
+  __shared__ double red[kSeqWaves * TEAMS][4];
+  __shared__ unsigned wmx[TEAMS][2][2];  // per-position max |P|^2, max |O_j|^2 (double-buffered by round parity)
+  __shared__ int nlev, nrounds;
   char* base = reinterpret_cast<char*>(dyn);
-  const SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes);
+  const SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes, TEAMS);
   float2* Ol = reinterpret_cast<float2*>(base + L.obj);
   float2* Pl = reinterpret_cast<float2*>(base + L.probe);
-  float2* Rl = reinterpret_cast<float2*>(base + L.res);
   int2* posl = reinterpret_cast<int2*>(base + L.pos);  // window corner in the box, x < 0: no position
   int* jl = reinterpret_cast<int*>(base + L.jidx);     // position index of each step
+  int* lvl = reinterpret_cast<int*>(base + L.lvl);
+  int* sched = reinterpret_cast<int*>(base + L.sched);
+  int* lstart = reinterpret_cast<int*>(base + L.lstart);
+  int* rtab = reinterpret_cast<int*>(base + L.rtab);
+  const int ldo = L.ldo, ldp = L.ldp;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int w = tid >> 6;
   const int lane = lane_id();
+  // wave w runs on SIMD w % 4; the second team's roles are rotated by two so
+  // that the two teams' forward waves (roles 0 and 1) sit on different SIMDs
+  const int team = w / kSeqWaves, wl = (w + team * (kSeqWaves / 2)) % kSeqWaves;
+  float2* Rl = reinterpret_cast<float2*>(base + L.res + (size_t)team * (((size_t)a.m * a.m * 8 + 255) & ~size_t(255)));
   // load: tables (verbatim), probe, object box, the order's positions;
   // clear the per-position slots
   {
@@ -574,9 +615,9 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a
     f32x4* ftl = reinterpret_cast<f32x4*>(base + L.ft);
     for (size_t i = tid; i < fa_bytes / 16; i += nt) fal[i] = fa[i];
     for (size_t i = tid; i < ft_bytes / 16; i += nt) ftl[i] = ft[i];
-    for (int i = tid; i < a.n * a.n; i += nt) Pl[i] = a.P[i];
+    for (int i = tid; i < a.n * a.n; i += nt) Pl[(i / a.n) * ldp + i % a.n] = a.P[i];
     for (int i = tid; i < a.bb_h * a.bb_w; i += nt)
-      Ol[i] = a.O[(size_t)(a.bb_r0 + i / a.bb_w) * a.W + a.bb_c0 + i % a.bb_w];
+      Ol[(i / a.bb_w) * ldo + i % a.bb_w] = a.O[(size_t)(a.bb_r0 + i / a.bb_w) * a.W + a.bb_c0 + i % a.bb_w];
     for (int t = tid; t < a.J; t += nt) {
       bool valid;
       const int j = pos_index(a.order, a.J, t, 0, &valid);
@@ -584,132 +625,224 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a
       posl[t] = valid ? make_int2(ps.x - a.bb_r0, ps.y - a.bb_c0) : make_int2(-1, 0);
       jl[t] = j;
     }
-    for (int i = tid; i < a.J * 4; i += nt) a.phi_part[i] = 0.0;
-    if (tid < 4) wmx[tid >> 1][tid & 1] = 0u;
+    if (tid < 4 * TEAMS) (&wmx[0][0][0])[tid] = 0u;
+    if constexpr (TEAMS > 1)
+      for (int i = tid; i <= a.J; i += nt) lstart[i] = 0;
   }
   __syncthreads();
+  if constexpr (TEAMS > 1) {
+    // levels, by the first wave in sweep order; a skipped entry touches
+    // nothing and takes level 0
+    if (w == 0) {
+      volatile int* lev = lvl;
+      int top = 0;
+      for (int t = 0; t < a.J; ++t) {
+        const int2 pt = posl[t];
+        int l = 0;
+        if (pt.x >= 0)
+          for (int u = lane; u < t; u += 64) {
+            const int2 pu = posl[u];
+            if (pu.x >= 0 && abs(pu.x - pt.x) < a.n && abs(pu.y - pt.y) < a.n) l = max(l, lev[u] + 1);
+          }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) l = max(l, __shfl_xor(l, off, 64));
+        if (lane == 0) lev[t] = l;
+        top = max(top, l);
+      }
+      if (lane == 0) nlev = top + 1;
+    }
+    __syncthreads();
+    // stable counting sort of the steps by level (sweep order inside a
+    // level, so that each team's share of the sweep is fixed)
+    for (int t = tid; t < a.J; t += nt) atomicAdd(&lstart[lvl[t] + 1], 1);
+    __syncthreads();
+    if (tid == 0)
+      for (int l = 1; l <= nlev; ++l) lstart[l] += lstart[l - 1];
+    __syncthreads();
+    for (int t = tid; t < a.J; t += nt) {
+      const int l = lvl[t];
+      int before = 0;
+      for (int u = 0; u < t; ++u) before += lvl[u] == l;
+      sched[lstart[l] + before] = t;
+    }
+    __syncthreads();
+    // the levels as rounds of up to TEAMS steps
+    if (tid == 0) {
+      int r = 0;
+      for (int l = 0; l < nlev; ++l)
+        for (int sb = lstart[l]; sb < lstart[l + 1]; sb += TEAMS, ++r)
+          for (int k = 0; k < TEAMS; ++k) rtab[r * TEAMS + k] = sb + k < lstart[l + 1] ? sched[sb + k] : -1;
+      nrounds = r;
+    }
+    __syncthreads();
+  } else {
+    if (tid == 0) nrounds = a.J;
+    __syncthreads();
+  }
   const TabL FA{(lds_cptr)(base + L.fa)};
   const TabL FT{(lds_cptr)(base + L.ft)};
-  const int wc = w % WC, wr = w / WC;
-  const bool fwd_wave = w < WR * WC;
+  const int wc = wl % WC, wr = (wl / WC) % WR, kh = wl / (WC * WR);
+  const bool fwd_role = wl < WR * WC * KS;
+  const bool proj_role = fwd_role && wr == 0 && kh == 0;  // sums the partials and projects
+  const int pslot = kh * WR + wr;                         // partial index (0: the projecting wave)
+  auto forward = [&](const auto& src, f32x4(&Yre)[MT][CT], f32x4(&Yim)[MT][CT]) {
+    if constexpr (Orient<PR>::TR)
+      fwd_engine<PR, MT, CT>(src, a.nb, FA, wc * CT, Yre, Yim, wr, WR);
+    else
+      fwd_wave<MT, CT>(src, a.nb, FA, wc * CT, Yre, Yim, wr, WR, kh, KS);
+  };
   const int passes = a.probe_literal ? 2 : 1;
   const int m = a.m;
-  for (int t = 0; t < a.J; ++t) {
-    const int2 rc0 = posl[t];
-    const bool valid = rc0.x >= 0;
-    const int j = jl[t];
-    const int r = valid ? rc0.x : 0, c = rc0.y;
-    unsigned* mx = wmx[t & 1];
-    if (tid == 0) {  // the next position's maxima start from zero (last read two positions ago)
-      wmx[(t + 1) & 1][0] = 0u;
-      wmx[(t + 1) & 1][1] = 0u;
-    }
-    for (int pass = 0; pass < passes; ++pass) {
-      PieArgs b = a;
-      b.R = Rl;
-      if (a.probe_literal) {
-        b.probe_step = pass;
-        b.probe_pass = pass;
-      }
-      const bool track = b.norm || b.probe_step;
-      // the projection's amplitudes, requested before the products
+  // this team's step of each round (-1: idle), and the projection's
+  // amplitudes, requested one round ahead
+  auto step_of = [&](int rd) { return TEAMS > 1 ? rtab[rd * TEAMS + team] : rd; };
+  float avn[MT][CT][4];
+  auto load_amp = [&](int t) {
+    const bool on = t >= 0 && proj_role;
+    const int j = on ? jl[t] : 0;
+#pragma unroll
+    for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
+          avn[c1t][ct][i] = (on && rc.x < m && rc.y < m) ? a.amp[(size_t)j * m * m + (size_t)rc.x * m + rc.y] : 0.f;
+        }
+  };
+  // (the rounds exchange data through LDS only, so their barriers leave the
+  // amplitude prefetch in flight)
+  load_amp(step_of(0));
+  double phi_acc = 0.0;  // this lane's objective terms over the sweep (summed once at the end)
+  for (int round = 0; round < nrounds; ++round) {
+    {
+      const int t = step_of(round);
+      const bool active = t >= 0;  // uniform over the team
       float av[MT][CT][4];
-      if (fwd_wave && wr == 0) {
 #pragma unroll
-        for (int c1t = 0; c1t < MT; ++c1t)
+      for (int c1t = 0; c1t < MT; ++c1t)
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct)
+        for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
-              av[c1t][ct][i] = (rc.x < m && rc.y < m) ? a.amp[(size_t)j * m * m + (size_t)rc.x * m + rc.y] : 0.f;
-            }
+          for (int i = 0; i < 4; ++i) av[c1t][ct][i] = avn[c1t][ct][i];
+      if (round + 1 < nrounds) load_amp(step_of(round + 1));
+      const int2 rc0 = posl[active ? t : 0];
+      const bool valid = active && rc0.x >= 0;
+      const int r = valid ? rc0.x : 0, c = valid ? rc0.y : 0;
+      unsigned* mx = wmx[team][round & 1];
+      if (wl == 0 && lane == 0) {  // the next round's maxima start from zero (last read two rounds ago)
+        wmx[team][(round + 1) & 1][0] = 0u;
+        wmx[team][(round + 1) & 1][1] = 0u;
       }
-      f32x4 Yre[MT][CT], Yim[MT][CT];
-      if (fwd_wave) {
-        if (track) {
-          GatherTrackSrc<EXACT> src{{Ol, Pl, a.bb_w, b.n, r, c}, 0.f, 0.f};
-          fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
-          if (wc == 0) {
-            const float mp = wave_max(src.mp), mo = wave_max(src.mo);
-            if (lane == 0) {
-              atomicMax(&mx[0], __float_as_uint(mp));
-              atomicMax(&mx[1], __float_as_uint(mo));
+      for (int pass = 0; pass < passes; ++pass) {
+        PieArgs b = a;
+        b.R = Rl;
+        if (a.probe_literal) {
+          b.probe_step = pass;
+          b.probe_pass = pass;
+        }
+        const bool track = b.norm || b.probe_step;
+        f32x4 Yre[MT][CT], Yim[MT][CT];
+        if (active && fwd_role) {
+          if (track) {
+            GatherTrackSrc<EXACT> src{{Ol, Pl, ldo, b.n, r, c, ldp}, 0.f, 0.f};
+            forward(src, Yre, Yim);
+            if (wc == 0) {
+              const float mp = wave_max(src.mp), mo = wave_max(src.mo);
+              if (lane == 0) {
+                atomicMax(&mx[0], __float_as_uint(mp));
+                atomicMax(&mx[1], __float_as_uint(mo));
+              }
+            }
+          } else {
+            GatherSrc<EXACT> src{Ol, Pl, ldo, b.n, r, c, ldp};
+            forward(src, Yre, Yim);
+          }
+          if (NP > 1 && pslot > 0) {
+            f32x4* dst = part[team] + ((size_t)((pslot - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+            for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+              for (int b1 = 0; b1 < CT; ++b1) {
+                dst[((a1 * CT + b1) * 2 + 0) * 64 + lane] = Yre[a1][b1];
+                dst[((a1 * CT + b1) * 2 + 1) * 64 + lane] = Yim[a1][b1];
+              }
+          }
+        }
+        lds_barrier();
+        if (active && proj_role) {
+#pragma unroll
+          for (int rr = 1; rr < NP; ++rr) {
+            const f32x4* src = part[team] + ((size_t)((rr - 1) * WC + wc) * MT * CT * 2) * 64;
+#pragma unroll
+            for (int a1 = 0; a1 < MT; ++a1)
+#pragma unroll
+              for (int b1 = 0; b1 < CT; ++b1) {
+                Yre[a1][b1] += src[((a1 * CT + b1) * 2 + 0) * 64 + lane];
+                Yim[a1][b1] += src[((a1 * CT + b1) * 2 + 1) * 64 + lane];
+              }
+          }
+          double phi = 0.0;
+#pragma unroll
+          for (int c1t = 0; c1t < MT; ++c1t)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
+                if (rc.x < m && rc.y < m)
+                  phi += pie_project_amp(b, 0, valid, rc.x, rc.y, Yre[c1t][ct][i], Yim[c1t][ct][i], av[c1t][ct][i]);
+              }
+          if (!b.probe_pass) phi_acc += phi;
+        }
+        lds_barrier();
+        if (active) {
+          double regP = 0.0, regO = 0.0;
+          if (b.norm) {
+            regP = b.alpha * (double)__uint_as_float(mx[0]);
+            regO = b.alpha * (double)__uint_as_float(mx[1]);
+          }
+          UpdateSink sink{Ol, Pl, b.n, ldo, r, c, b.norm, b.probe_step, (int)valid, b.probe_pass,
+                          b.inv_n2, b.beta, b.gamma, regP, regO, ldp};
+          ResSrc rsrc{Rl, m};
+          bool shared_tiles = false;
+          if constexpr (!Orient<PR>::TR) {
+            // few column tiles (FP32): two waves per tile, each taking every
+            // other row tile of it
+            if (2 * b.nb <= kSeqWaves) {
+              shared_tiles = true;
+              const int kt2 = wl % b.nb, half = wl / b.nb;
+              if (half < 2) adj_wave_tile<MT, ResSrc, UpdateSink, TabL, 1>(rsrc, b.nb, FT, kt2, sink, half, 2);
             }
           }
-        } else {
-          GatherSrc<EXACT> src{Ol, Pl, a.bb_w, b.n, r, c};
-          fwd_engine<PR, MT, CT>(src, b.nb, FA, wc * CT, Yre, Yim, wr, WR);
+          if (!shared_tiles)
+            for (int kt2 = wl; kt2 < b.nb; kt2 += kSeqWaves) adj_engine<PR, MT>(rsrc, b.nb, FT, kt2, sink);
         }
-        if (WR > 1 && wr > 0) {
-          f32x4* dst = part + ((size_t)((wr - 1) * WC + wc) * MT * CT * 2) * 64;
-#pragma unroll
-          for (int a1 = 0; a1 < MT; ++a1)
-#pragma unroll
-            for (int b1 = 0; b1 < CT; ++b1) {
-              dst[((a1 * CT + b1) * 2 + 0) * 64 + lane] = Yre[a1][b1];
-              dst[((a1 * CT + b1) * 2 + 1) * 64 + lane] = Yim[a1][b1];
-            }
-        }
+        lds_barrier();
       }
-      __syncthreads();
-      if (fwd_wave && wr == 0) {
-#pragma unroll
-        for (int rr = 1; rr < WR; ++rr) {
-          const f32x4* src = part + ((size_t)((rr - 1) * WC + wc) * MT * CT * 2) * 64;
-#pragma unroll
-          for (int a1 = 0; a1 < MT; ++a1)
-#pragma unroll
-            for (int b1 = 0; b1 < CT; ++b1) {
-              Yre[a1][b1] += src[((a1 * CT + b1) * 2 + 0) * 64 + lane];
-              Yim[a1][b1] += src[((a1 * CT + b1) * 2 + 1) * 64 + lane];
-            }
-        }
-        double phi = 0.0;
-#pragma unroll
-        for (int c1t = 0; c1t < MT; ++c1t)
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
-              if (rc.x < m && rc.y < m)
-                phi += pie_project_amp(b, 0, valid, rc.x, rc.y, Yre[c1t][ct][i], Yim[c1t][ct][i], av[c1t][ct][i]);
-            }
-        phi = wave_sum(phi);
-        if (lane == 0 && valid && !b.probe_pass) b.phi_part[(size_t)j * 4 + wc] = phi;
-      }
-      __syncthreads();
-      double regP = 0.0, regO = 0.0;
-      if (b.norm) {
-        regP = b.alpha * (double)__uint_as_float(mx[0]);
-        regO = b.alpha * (double)__uint_as_float(mx[1]);
-      }
-      UpdateSink sink{Ol, Pl, b.n, a.bb_w, r, c, b.norm, b.probe_step, (int)valid, b.probe_pass,
-                      b.inv_n2, b.beta, b.gamma, regP, regO};
-      ResSrc rsrc{Rl, m};
-      for (int kt2 = w; kt2 < b.nb; kt2 += kSeqWaves) adj_engine<PR, MT>(rsrc, b.nb, FT, kt2, sink);
-      __syncthreads();
     }
   }
+  __syncthreads();
   // statistics against the object still in global memory, then write back:
   // {Phi, ||O_after - O_before||^2, ||O_before||^2, non-finite}
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = tid; i < a.J * 4; i += nt) v[0] += a.phi_part[i];
+  double v[4] = {phi_acc, 0.0, 0.0, 0.0};
   const int total = a.H * a.W;  // at most kSeqLdsMaxObject
   for (int i = tid; i < total; i += nt) {
     const int y = i / a.W, x = i - y * a.W;
     const float2 z = a.O[i];
     float2 o = z;
     const int yy = y - a.bb_r0, xx = x - a.bb_c0;
-    if (yy >= 0 && yy < a.bb_h && xx >= 0 && xx < a.bb_w) o = Ol[(size_t)yy * a.bb_w + xx];
+    if (yy >= 0 && yy < a.bb_h && xx >= 0 && xx < a.bb_w) o = Ol[yy * ldo + xx];
     const double dx = (double)o.x - z.x, dy = (double)o.y - z.y;
     v[1] += dx * dx + dy * dy;
     v[2] += (double)z.x * z.x + (double)z.y * z.y;
     v[3] += (isfinite(o.x) && isfinite(o.y)) ? 0.0 : 1.0;
   }
   if (a.probe_step)
-    for (int i = tid; i < a.n * a.n; i += nt) v[3] += (isfinite(Pl[i].x) && isfinite(Pl[i].y)) ? 0.0 : 1.0;
+    for (int i = tid; i < a.n * a.n; i += nt) {
+      const float2 pv = Pl[(i / a.n) * ldp + i % a.n];
+      v[3] += (isfinite(pv.x) && isfinite(pv.y)) ? 0.0 : 1.0;
+    }
 #pragma unroll
   for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
   if (lane == 0)
@@ -718,7 +851,7 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a
   __syncthreads();
   if (tid == 0) {
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < kSeqWaves; ++k)
+    for (int k = 0; k < kSeqWaves * TEAMS; ++k)
       for (int q = 0; q < 4; ++q) s4[q] += red[k][q];
     a.stats[0] = s4[0] / ((double)a.J * a.period * a.period);
     a.stats[1] = s4[1];
@@ -726,24 +859,37 @@ __global__ __launch_bounds__(64 * kSeqWaves) void k_pie_sequential_lds(PieArgs a
     a.stats[3] = s4[3];
   }
   for (int i = tid; i < a.bb_h * a.bb_w; i += nt)
-    a.O[(size_t)(a.bb_r0 + i / a.bb_w) * a.W + a.bb_c0 + i % a.bb_w] = Ol[i];
+    a.O[(size_t)(a.bb_r0 + i / a.bb_w) * a.W + a.bb_c0 + i % a.bb_w] = Ol[(i / a.bb_w) * ldo + i % a.bb_w];
   if (a.probe_step)
-    for (int i = tid; i < a.n * a.n; i += nt) a.P[i] = Pl[i];
+    for (int i = tid; i < a.n * a.n; i += nt) a.P[i] = Pl[(i / a.n) * ldp + i % a.n];
 }
 
 template <class PR, int MT>
 bool sequential_lds_prec(const PieArgs& a, size_t fa_bytes, size_t ft_bytes, hipStream_t st) {
-  const SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes);
+  // side-by-side teams only without probe step (which couples every
+  // position), for one tile of kept coefficients per axis (two tiles need
+  // more registers than two waves per SIMD leave), and where their LDS fits
+  int teams = (MT == 1 && !a.probe_step && a.J <= kSeqLevelMaxJ) ? 2 : 1;
+  SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes, teams);
+  if (teams == 2 && L.total > kSeqLdsBytes) {
+    teams = 1;
+    L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes, 1);
+  }
   // (the statistics read the whole object from one workgroup)
   if (L.total > kSeqLdsBytes || (size_t)a.H * a.W > kSeqLdsMaxObject) return false;
-  auto launch = [&](auto kernel) {
+  auto launch = [&](auto kernel, int nteams) {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)L.total) != hipSuccess)
       return false;
-    hipLaunchKernelGGL(kernel, dim3(1), dim3(64 * kSeqWaves), L.total, st, a, fa_bytes, ft_bytes);
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(64 * kSeqWaves * nteams), L.total, st, a, fa_bytes, ft_bytes);
     return true;
   };
-  return a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true>) : launch(k_pie_sequential_lds<PR, MT, false>);
+  if constexpr (MT == 1)
+    if (teams == 2)
+      return a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true, 2>, 2)
+                           : launch(k_pie_sequential_lds<PR, MT, false, 2>, 2);
+  return a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true, 1>, 1)
+                       : launch(k_pie_sequential_lds<PR, MT, false, 1>, 1);
 }
 
 template <class PR, int MT>

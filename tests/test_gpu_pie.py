@@ -143,6 +143,27 @@ def test_at_scale_one_sweep(pk):
     Or, _, sr = opie.pie_sweep(case["init"], case["probe"], case["pos"], amp, m, **params)
     assert rel(O, Or) <= 1e-5
     assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
+    # ||dO||^2 and ||O||^2 over the whole object (the scan leaves a border
+    # of the object unlit, which the update's statistics must include)
+    assert abs(st[0][1] - sr[1]) <= 1e-4 * sr[1]
+    assert abs(st[0][2] - sr[2]) <= 1e-6 * sr[2]
+    assert st[0][3] == 0
+
+
+@pytest.mark.parametrize("norm", [0, 1])
+def test_single_position_with_larger_batch(pk, tiny, norm):
+    # one position and batch > 1: the chunk is that position alone, updated
+    # in place; the sweep statistics still cover its change
+    m = tiny["m"]
+    case = dict(tiny, pos=tiny["pos"][5:6])
+    A, amp = amps(pk, tiny["intensity"][5:6], m)
+    params = dict(batch=4, norm=norm, beta=1.0, gamma=0.0, alpha=1e-3)
+    O, _, st = run_gpu(pk, case, tiny["init"], tiny["probe"], A, m, pk.PieParams(**params))
+    Or, _, sr = opie.pie_sweep(tiny["init"], tiny["probe"], case["pos"], amp, m, **params)
+    assert rel(O, Or) <= 1e-5
+    assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
+    assert sr[1] > 0 and abs(st[0][1] - sr[1]) <= 1e-4 * sr[1]
+    assert abs(st[0][2] - sr[2]) <= 1e-6 * sr[2]
 
 
 def test_ragged_window_and_sizes(pk):
@@ -213,8 +234,9 @@ def test_at_scale_one_sweep_split(pk, precision, tol):
 
 @pytest.mark.parametrize("params", [dict(batch=9, norm=1, beta=1.0, alpha=1e-3),
                                     dict(batch=64, norm=0, beta=0.05),
-                                    dict(batch=5, norm=1, beta=0.8, gamma=0.5, alpha=1e-3)],
-                         ids=["b9-norm", "b64-plain", "b5-probe"])
+                                    dict(batch=5, norm=1, beta=0.8, gamma=0.5, alpha=1e-3),
+                                    dict(batch=1, norm=0, beta=1.0)],
+                         ids=["b9-norm", "b64-plain", "b5-probe", "b1-sequential"])
 def test_order_with_missing_position_reuses_workspace(pk, tiny, params):
     """A sweep with a full permutation leaves every rank in the workspace;
     a second sweep over the same workspace whose order drops one position
