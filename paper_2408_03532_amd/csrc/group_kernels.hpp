@@ -45,7 +45,11 @@ __device__ __forceinline__ void fwd_item(const GroupClass& c, const GroupItem& i
   const int c2t0 = it.slot * CT;
   PlainSrc<EXACT> src{in + it.in_off, c.n};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, c.nb, TabG{static_cast<const char*>(c.tab)}, c2t0, Yre, Yim);
+  const TabG tab{static_cast<const char*>(c.tab)};
+  if constexpr (Orient<PR>::TR)
+    fwd_engine<PR, MT, CT>(src, c.nb, tab, c2t0, Yre, Yim);
+  else  // FP32: three products for every block (the kernel runs one wave per SIMD)
+    fwd_wave<MT, CT, PlainSrc<EXACT>, TabG, true>(src, c.nb, tab, c2t0, Yre, Yim);
   const int lane = lane_id();
   float2* o = out + it.out_off;
   const int m = c.m;

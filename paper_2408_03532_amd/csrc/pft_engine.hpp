@@ -284,12 +284,14 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
 // ctiles x NB blocks.  c2t0: first column tile this wave owns; the wave
 // runs strips strip0, strip0 + sstep, ...
 // With kbs > 1 the wave sums column blocks kb0, kb0 + kbs, ... only: kbs
-// waves then hold partial results whose sum is the transform.
-template <int MT, int CT, class Src, class Tab>
+// waves then hold partial results whose sum is the transform.  WIDE: three
+// products also for up to 16 output tiles (about 440 registers, one wave
+// per SIMD; for kernels that run at that occupancy anyway).
+template <int MT, int CT, class Src, class Tab, bool WIDE = false>
 __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
                                          f32x4 (&Yim)[MT][CT], int strip0 = 0, int sstep = 1, int kb0 = 0,
                                          int kbs = 1) {
-  if constexpr (MT * CT <= 8)
+  if constexpr (MT * CT <= (WIDE ? 16 : 8))
     fwd_wave_gauss<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, kb0, kbs);
   else
     fwd_wave_four<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, kb0, kbs);
