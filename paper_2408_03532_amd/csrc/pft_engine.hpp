@@ -201,7 +201,7 @@ __device__ __forceinline__ void fwd_wave_gauss(const Src& src, int NB, const Tab
 // formed in a register), for wider output blocks.
 template <int MT, int CT, class Src, class Tab>
 __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab& FA, int c2t0, f32x4 (&Yre)[MT][CT],
-                                              f32x4 (&Yim)[MT][CT], int strip0, int sstep, int kb0 = 0, int kbs = 1) {
+                                              f32x4 (&Yim)[MT][CT], int strip0, int sstep) {
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -244,21 +244,17 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
     };
     Raw a0, a1;
     c4 f0[CT], f1[CT];
-    if (kb0 < NB) {
-      // column blocks kb0, kb0 + kbs, ... (all of them unless several waves
-      // share the strip's sum)
-      fetch(kb0, a0, f0);
-      int kb = kb0;
-      for (; kb + kbs < NB; kb += 2 * kbs) {
-        fetch(kb + kbs, a1, f1);
-        __builtin_amdgcn_sched_barrier(0);
-        stage1(a0, f0);
-        fetch(kb + 2 * kbs < NB ? kb + 2 * kbs : kb + kbs, a0, f0);
-        __builtin_amdgcn_sched_barrier(0);
-        stage1(a1, f1);
-      }
-      if (kb < NB) stage1(a0, f0);
+    fetch(0, a0, f0);
+    int kb = 0;
+    for (; kb + 1 < NB; kb += 2) {
+      fetch(kb + 1, a1, f1);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a0, f0);
+      fetch(kb + 2 < NB ? kb + 2 : kb + 1, a0, f0);
+      __builtin_amdgcn_sched_barrier(0);
+      stage1(a1, f1);
     }
+    if (kb < NB) stage1(a0, f0);
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
       c4 fb = FA.f32((size_t)c1t * NB + strip, lane);
@@ -283,8 +279,9 @@ __device__ __forceinline__ void fwd_wave_four(const Src& src, int NB, const Tab&
 // Forward engine.  NB = ceil(n/16) row strips / column blocks.  FA holds
 // ctiles x NB blocks.  c2t0: first column tile this wave owns; the wave
 // runs strips strip0, strip0 + sstep, ...
-// With kbs > 1 the wave sums column blocks kb0, kb0 + kbs, ... only: kbs
-// waves then hold partial results whose sum is the transform.  WIDE: three
+// With kbs > 1 (three-product form only) the wave sums column blocks kb0,
+// kb0 + kbs, ... only: kbs waves then hold partial results whose sum is the
+// transform.  WIDE: three
 // products also for up to 16 output tiles (about 440 registers, one wave
 // per SIMD; for kernels that run at that occupancy anyway).
 template <int MT, int CT, class Src, class Tab, bool WIDE = false>
@@ -294,7 +291,7 @@ __device__ __forceinline__ void fwd_wave(const Src& src, int NB, const Tab& FA, 
   if constexpr (MT * CT <= (WIDE ? 16 : 8))
     fwd_wave_gauss<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, kb0, kbs);
   else
-    fwd_wave_four<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep, kb0, kbs);
+    fwd_wave_four<MT, CT>(src, NB, FA, c2t0, Yre, Yim, strip0, sstep);  // (kbs == 1 only)
 }
 
 // Forward engine for long windows whose twiddle table does not stay in the
@@ -322,11 +319,14 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
       const int sr = base + r * sstep;
       rows[r] = (sr < NB ? sr : base) * 16 + r16;
     }
-    f32x4 Tre[RS][CT], Tim[RS][CT];
+    // stage 1 in three products (Gauss): k1 in T1, k2 in Tre, k3 in Tim
+    // until the strip is done
+    f32x4 T1[RS][CT], Tre[RS][CT], Tim[RS][CT];
 #pragma unroll
     for (int r = 0; r < RS; ++r)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
+        T1[r][ct] = zero4();
         Tre[r][ct] = zero4();
         Tim[r][ct] = zero4();
       }
@@ -336,21 +336,21 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
 #pragma unroll
       for (int r = 0; r < RS; ++r) a[r] = combine(src, raw[r]);
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s) {
+        float fs[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) fs[ct] = f[ct].v[s].x + f[ct].v[s].y;
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
-          const float ar = a[r].v[s].x, ai = a[r].v[s].y, nai = -ai;
+          const float ar = a[r].v[s].x, ai = a[r].v[s].y, sab = ar + ai, dba = ai - ar;
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
-            Tre[r][ct] = mfma4(ar, f[ct].v[s].x, Tre[r][ct]);
-            Tim[r][ct] = mfma4(ar, f[ct].v[s].y, Tim[r][ct]);
-          }
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            Tre[r][ct] = mfma4(nai, f[ct].v[s].y, Tre[r][ct]);
-            Tim[r][ct] = mfma4(ai, f[ct].v[s].x, Tim[r][ct]);
+            T1[r][ct] = mfma4(ar, fs[ct], T1[r][ct]);
+            Tre[r][ct] = mfma4(sab, f[ct].v[s].y, Tre[r][ct]);
+            Tim[r][ct] = mfma4(dba, f[ct].v[s].x, Tim[r][ct]);
           }
         }
+      }
     };
     auto fetch = [&](int kb, Raw(&a)[RS], c4(&f)[CT]) {
 #pragma unroll
@@ -371,6 +371,14 @@ __device__ __forceinline__ void fwd_wave_rs(const Src& src, int NB, const Tab& F
       stage1(a1, f1);
     }
     if (kb < NB) stage1(a0, f0);
+    // T = (k1 - k2) + i (k1 + k3)
+#pragma unroll
+    for (int r = 0; r < RS; ++r)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        Tre[r][ct] = T1[r][ct] - Tre[r][ct];
+        Tim[r][ct] = T1[r][ct] + Tim[r][ct];
+      }
     // stage 2 per live strip: Y[c1 tile][own tiles] += F[c1 tile, strip] * T
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
@@ -628,15 +636,28 @@ __device__ __forceinline__ void adj_tiles_f32(const YSrc& ysrc, int NB, const Ta
       }
   }
   // stage 2: X_u[k1][k2] = sum_c1 conj(F[c1][k1]) S_u[c1][k2], one row tile
-  // at a time, the next block fetched while this one's products issue
+  // at a time, the next block fetched while this one's products issue; three
+  // products per complex product as in adj_stage2_gauss (S = a + ib:
+  // k1 = a (Re F - Im F), k2' = Im F (a + b), k3 = Re F (b - a),
+  // Re X = k1 + k2', Im X = k1 + k3), so Sim is turned into a + b and Sre
+  // keeps a beside b - a
+  f32x4 Sdif[K2][MT];
+#pragma unroll
+  for (int u = 0; u < K2; ++u)
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      Sdif[u][a] = Sim[u][a] - Sre[u][a];
+      Sim[u][a] = Sim[u][a] + Sre[u][a];
+    }
   c4 fb[2];
   fb[0] = FT.f32(0, lane);
   for (int k1t = 0; k1t < NB; ++k1t) {
-    f32x4 Xre[K2], Xim[K2];
+    f32x4 X1[K2], X2[K2], X3[K2];
 #pragma unroll
     for (int u = 0; u < K2; ++u) {
-      Xre[u] = zero4();
-      Xim[u] = zero4();
+      X1[u] = zero4();
+      X2[u] = zero4();
+      X3[u] = zero4();
     }
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) {
@@ -647,21 +668,19 @@ __device__ __forceinline__ void adj_tiles_f32(const YSrc& ysrc, int NB, const Ta
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float fr = fb[cur].v[i].x, fi = fb[cur].v[i].y;
+        const float fr = fb[cur].v[i].x, fi = fb[cur].v[i].y, fd = fr - fi;
 #pragma unroll
         for (int u = 0; u < K2; ++u) {
-          const float sr = Sre[u][c1t][i], si = Sim[u][c1t][i];
-          Xre[u] = mfma4(fr, sr, Xre[u]);
-          Xim[u] = mfma4(fr, si, Xim[u]);
-          Xre[u] = mfma4(fi, si, Xre[u]);
-          Xim[u] = mfma4(-fi, sr, Xim[u]);
+          X1[u] = mfma4(fd, Sre[u][c1t][i], X1[u]);
+          X2[u] = mfma4(fi, Sim[u][c1t][i], X2[u]);
+          X3[u] = mfma4(fr, Sdif[u][c1t][i], X3[u]);
         }
       }
     }
     if constexpr ((MT & 1) != 0) fb[0] = fb[1];
 #pragma unroll
     for (int u = 0; u < K2; ++u)
-      if (kt2_0 + u < NB) sink.template put<false>(k1t, kt2_0 + u, Xre[u], Xim[u]);
+      if (kt2_0 + u < NB) sink.template put<false>(k1t, kt2_0 + u, X1[u] + X2[u], X1[u] + X3[u]);
   }
 }
 
