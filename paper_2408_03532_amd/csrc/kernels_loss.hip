@@ -18,15 +18,15 @@
 
 namespace pftpie {
 
-template <class PR, int MT, int CT, bool EXACT>
-__global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(LossArgs a) {
-  const int j = blockIdx.x;
-  const int w = threadIdx.x >> 6;
-  const int c2t0 = w * CT;
+// Forward of position j for column-tile group wslot (tiles wslot * CT ...):
+// u_j (optional) and the group's partial loss at part[j][wslot].
+template <class PR, int MT, int CT, bool EXACT, class Tab>
+__device__ __forceinline__ void loss_fwd_item(const LossArgs& a, const Tab& T, int j, int wslot) {
+  const int c2t0 = wslot * CT;
   const int2 ps = a.pos[j];
   GatherSrc<EXACT> src{a.O, a.P, a.W, a.n, ps.x, ps.y, a.n};
   f32x4 Yre[MT][CT], Yim[MT][CT];
-  fwd_engine<PR, MT, CT>(src, a.nb, TabG{static_cast<const char*>(a.fa)}, c2t0, Yre, Yim);
+  fwd_engine<PR, MT, CT>(src, a.nb, T, c2t0, Yre, Yim, 0, 1, j % a.nb);
   const int lane = lane_id();
   const int m = a.m;
   const float* amp = a.amp + (size_t)j * m * m;
@@ -49,7 +49,34 @@ __global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(Loss
       }
     }
   part = wave_sum(part);
-  if (lane == 0) a.part[(size_t)j * 4 + w] = part;
+  if (lane == 0) a.part[(size_t)j * 4 + wslot] = part;
+}
+
+template <class PR, int MT, int CT, bool EXACT>
+__global__ __launch_bounds__(64 * ((MT + CT - 1) / CT)) void k_loss_forward(LossArgs a) {
+  loss_fwd_item<PR, MT, CT, EXACT>(a, TabG{static_cast<const char*>(a.fa)}, blockIdx.x, threadIdx.x >> 6);
+}
+
+// Persistent forms: one workgroup per compute unit copies the twiddle table
+// into LDS, then its waves pull work items (position, column-tile group) or
+// positions.  Used when the table fits LDS and the windows are whole
+// 16-pixel tiles.
+__device__ __forceinline__ void loss_table_to_lds(f32x4* smem, const void* tab, size_t bytes) {
+  const f32x4* t = static_cast<const f32x4*>(tab);
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) smem[i] = t[i];
+  __syncthreads();
+}
+
+template <class PR, int MT, int CT, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_loss_forward_lds(LossArgs a) {
+  extern __shared__ f32x4 smem[];
+  loss_table_to_lds(smem, a.fa, a.fa_bytes);
+  const TabL T{(lds_cptr)smem};
+  constexpr int W = (MT + CT - 1) / CT;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int64_t items = (int64_t)a.J * W;
+  for (int64_t it = (int64_t)blockIdx.x * nwaves + wave; it < items; it += (int64_t)gridDim.x * nwaves)
+    loss_fwd_item<PR, MT, CT, true>(a, T, (int)(it / W), (int)(it % W));
 }
 
 // G = 2 (u - a sgn(u)) built on the fly from u_j and a_j (sgn(0) = 0).
@@ -90,6 +117,31 @@ struct RSink {
     }
   }
 };
+
+// Whole window per wave (m <= 64 in 16-pixel tiles): the gradient
+// coefficients stay in registers for every column tile.  FP32 with `share`
+// = 2: two waves per window, each taking every other column tile (work
+// items (position, half)), so that fewer positions than twice the wave
+// slots still fill the compute units.
+template <class PR, int MT, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_loss_adjoint_lds(LossArgs a, int share) {
+  extern __shared__ f32x4 smem[];
+  loss_table_to_lds(smem, a.ft, a.ft_bytes);
+  const TabL T{(lds_cptr)smem};
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const size_t mm = (size_t)a.m * a.m;
+  const float scale = a.scale_dev ? (float)a.scale_dev[0] : 1.f;
+  const int items = a.J * share;
+  for (int it = blockIdx.x * nwaves + wave; it < items; it += gridDim.x * nwaves) {
+    const int j = it / share, part = it % share;
+    GradSrc src{a.Uc + (size_t)j * mm, a.amp + (size_t)j * mm, a.m};
+    RSink sink{a.Rbuf + (size_t)j * a.n * a.n, a.n, scale};
+    if constexpr (Orient<PR>::TR)
+      adj_patch_split<PR, MT>(src, a.nb, T, sink);
+    else
+      adj_patch_f32<MT, 1>(src, a.nb, T, sink, part, share);
+  }
+}
 
 template <class PR, int MT>
 __global__ __launch_bounds__(256) void k_loss_adjoint(LossArgs a) {
@@ -186,10 +238,33 @@ __global__ __launch_bounds__(256) void k_loss_clear_parts(LossArgs a) {
     a.part[t] = 0.0;
 }
 
+// Persistent launch of `kernel` with `tab_bytes` of dynamic LDS: at most one
+// workgroup per compute unit, fewer when the items are few.
+template <class K, class... Extra>
+static bool launch_lds(K kernel, const LossArgs& a, size_t tab_bytes, int64_t items, int threads, hipStream_t st,
+                       Extra... extra) {
+  if (tab_bytes > kMaxLdsTable ||
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)tab_bytes) != hipSuccess)
+    return false;
+  const int64_t waves = threads / 64;
+  int64_t grid = (items + waves - 1) / waves;
+  if (grid > a.num_cu) grid = a.num_cu;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), tab_bytes, st, a, extra...);
+  return true;
+}
+
+// windows of whole 16-pixel tiles (the persistent forward runs the
+// unchecked operand loads)
+static bool loss_tiles_exact(const LossArgs& a) { return a.n % 16 == 0; }
+
 template <class PR, int MT>
 static void fwd_prec(const LossArgs& a, hipStream_t st) {
   constexpr int CT = (MT <= 2) ? MT : 2;
   constexpr int W = (MT + CT - 1) / CT;
+  if (loss_tiles_exact(a) &&
+      launch_lds(k_loss_forward_lds<PR, MT, CT, 512>, a, a.fa_bytes, (int64_t)a.J * W, 512, st))
+    return;
   if (a.n % 16 == 0)
     hipLaunchKernelGGL((k_loss_forward<PR, MT, CT, true>), dim3(a.J), dim3(64 * W), 0, st, a);
   else
@@ -208,6 +283,24 @@ static void fwd_mt(const LossArgs& a, hipStream_t st) {
 
 template <int MT>
 static void adj_mt(const LossArgs& a, hipStream_t st) {
+  if constexpr (MT <= 4) {
+    if (a.m % 16 == 0 && a.n % 16 == 0) {
+      // whole window per wave: the split coefficients of m = 48, 64 take
+      // most of the registers (one wave per SIMD); otherwise two fit
+      constexpr int TH = MT <= 2 ? 512 : 256;
+      bool done = false;
+      if (a.prec == PFTPIE_SPLIT_BF16) {
+        done = launch_lds(k_loss_adjoint_lds<PrecBF16, MT, TH>, a, a.ft_bytes, a.J, TH, st, 1);
+      } else if (a.prec == PFTPIE_SPLIT_FP16) {
+        done = launch_lds(k_loss_adjoint_lds<PrecF16, MT, TH>, a, a.ft_bytes, a.J, TH, st, 1);
+      } else {
+        // two waves per window while the positions alone leave wave slots idle
+        const int share = (a.J < 2 * 8 * a.num_cu && a.nb >= 2) ? 2 : 1;
+        done = launch_lds(k_loss_adjoint_lds<PrecF32, MT, 512>, a, a.ft_bytes, (int64_t)a.J * share, 512, st, share);
+      }
+      if (done) return;
+    }
+  }
   dim3 grid(a.J), block(64 * adj_waves(a.nb));
   if (a.prec == PFTPIE_SPLIT_BF16)
     hipLaunchKernelGGL((k_loss_adjoint<PrecBF16, MT>), grid, block, 0, st, a);

@@ -10,6 +10,8 @@ struct LossArgs {
   const int2* pos;
   const void* fa;
   const void* ft;
+  size_t fa_bytes, ft_bytes;  // twiddle table sizes (the persistent kernels hold them in LDS)
+  int num_cu;
   int prec;
   const float2* O;
   const float2* P;

@@ -688,7 +688,8 @@ __device__ __forceinline__ void adj_tiles_f32(const YSrc& ysrc, int NB, const Ta
 // stay in registers (128 at MT = 4) for every column tile kt2, so the wave
 // issues no memory loads between its output stores.
 template <int MT, int K1, class YSrc, class Sink, class Tab>
-__device__ __forceinline__ void adj_patch_f32(const YSrc& ysrc, int NB, const Tab& FT, Sink& sink) {
+__device__ __forceinline__ void adj_patch_f32(const YSrc& ysrc, int NB, const Tab& FT, Sink& sink, int kt_first = 0,
+                                              int kt_step = 1) {
   static_assert(MT <= 4, "larger windows do not fit in registers");
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
@@ -697,7 +698,9 @@ __device__ __forceinline__ void adj_patch_f32(const YSrc& ysrc, int NB, const Ta
   for (int kb = 0; kb < MT; ++kb)
 #pragma unroll
     for (int c1t = 0; c1t < MT; ++c1t) y[kb][c1t] = ysrc.load(c1t * 16 + r16, kb * 16 + 4 * g);
-  for (int kt2 = 0; kt2 < NB; ++kt2) {
+  // column tiles kt_first, kt_first + kt_step, ... (several waves may share
+  // a window)
+  for (int kt2 = kt_first; kt2 < NB; kt2 += kt_step) {
     // stage 1, S = Y conj(F), in three products: data y = a + ib, twiddle
     // conj(F) = c + id (c = Re F, d = -Im F):
     //   k1 = c (a + b),  k2' = a (Re F + Im F),  k3 = b (Re F - Im F),

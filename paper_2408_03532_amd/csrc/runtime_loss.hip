@@ -60,6 +60,9 @@ LossArgs base_args(const pie_scan_s* s, const void* O, const void* P, const floa
   a.pos = s->pos;
   a.fa = pl->fa;
   a.ft = pl->ft;
+  a.fa_bytes = pl->fa_bytes;
+  a.ft_bytes = pl->ft_bytes;
+  a.num_cu = pl->num_cu;
   a.prec = pl->prec;
   a.O = static_cast<const float2*>(O);
   a.P = static_cast<const float2*>(P);

@@ -329,3 +329,28 @@ def test_sequential_sweep_on_a_large_object(pk, precision, tol, params):
     Or, Pr, sr = opie.pie_sweep(obj, probe, pos, amp, m, **params)
     assert rel(O, Or) <= tol and rel(P, Pr) <= tol
     assert abs(st[0][0] - sr[0]) <= tol * sr[0] and abs(st[0][1] - sr[1]) <= 1e-4 * sr[1]
+
+
+@pytest.mark.parametrize("norm", [0, 1])
+def test_sequential_sweep_of_mixed_overlap(pk, tiny, norm):
+    """batch = 1 over a scan whose windows partly overlap: a 3 x 3 grid of
+    disjoint windows (step 40 > n = 32) and a cluster of four overlapping
+    ones, in a shuffled order with one entry outside [0, J).  Positions of
+    disjoint windows run side by side on the device; the result must be the
+    one-by-one sweep in the given order."""
+    m = tiny["m"]
+    grid = [(4 + 40 * a, 4 + 40 * b) for a in range(3) for b in range(3)]
+    cluster = [(60, 60), (66, 62), (62, 70), (70, 68)]
+    pos = np.asarray(grid + cluster, dtype=np.int32)
+    J = len(pos)
+    inten = workloads.intensities(tiny["obj"], tiny["probe"], pos)
+    A, amp = amps(pk, inten, m)
+    case = dict(tiny, pos=pos)
+    order = np.random.default_rng(17).permutation(J).astype(np.int32)
+    order[5] = J + 3  # skipped
+    params = dict(batch=1, norm=norm, beta=1.0, alpha=0.1)
+    O, _, st = run_gpu(pk, case, tiny["init"], tiny["probe"], A, m, pk.PieParams(**params), order=order)
+    Or, _, sr = opie.pie_sweep(tiny["init"], tiny["probe"], pos, amp, m, order=order, **params)
+    assert rel(O, Or) <= 1e-5
+    assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
+    assert abs(st[0][1] - sr[1]) <= 1e-4 * sr[1]
