@@ -216,25 +216,42 @@ __device__ __forceinline__ void fwd_wave_split_pass(const Src& src, int NB, cons
     // after it were skipped and drain the ring every turn)
     // column blocks in the order rot, rot + 1, ... (mod NB): waves that start
     // at different offsets of their patches spread over the memory channels
-    const int nq = nstrips * NB;
-    auto load_a = [&](int q) {
-      q = q < nq ? q : nq - 1;
-      const int j = q / NB;
-      int k = q - j * NB + rot;
+    // The loaders take chunk offsets q < 2 RING <= NB from the start of the
+    // current ring turn (strip tj, column block tk), so a chunk is at most
+    // one strip ahead: no division per chunk.
+    int tj = 0, tk = 0;
+    auto chunk = [&](int q, int& j, int& k) {
+      j = tj;
+      k = tk + q;
+      if (k >= NB) {
+        k -= NB;
+        ++j;
+      }
+      if (j >= nstrips) {  // past the wave's last chunk: reload it
+        j = nstrips - 1;
+        k = NB - 1;
+      }
+      k += rot;
       k = k < NB ? k : k - NB;
+    };
+    auto load_a = [&](int q) {
+      int j, k;
+      chunk(q, j, k);
       return load_raw(src, (strip0 + j * sstep) * 16 + r16, k * 16 + 4 * g);
     };
     auto load_f = [&](int q, TwS<PR>(&fr)[CT]) {
-      int k = (q < nq ? q : nq - 1) % NB + rot;
-      k = k < NB ? k : k - NB;
+      int j, k;
+      chunk(q, j, k);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) fr[ct] = FA.template s16<PR>((size_t)(c2t0 + ct) * NB + k, lane);
     };
     start(load_a, load_f);
     for (int j = 0; j < nstrips; ++j) {
-      for (int q0 = j * NB; q0 < (j + 1) * NB; q0 += RING) {
+      for (int k0 = 0; k0 < NB; k0 += RING) {
+        tj = j;
+        tk = k0;
 #pragma unroll
-        for (int u = 0; u < RING; ++u) run(load_a, load_f, q0, u);
+        for (int u = 0; u < RING; ++u) run(load_a, load_f, 0, u);
       }
       stage2(strip0 + j * sstep);
     }
