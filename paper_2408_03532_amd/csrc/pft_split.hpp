@@ -537,7 +537,8 @@ __device__ __forceinline__ void adj_wave_tile_split(const YSrc& ysrc, int NB, co
 // serve every column tile kt2, so the wave issues no memory loads between
 // its output stores and the stage-1 operand split is not repeated per tile.
 template <class PR, int MT, class YSrc, class Sink, class Tab>
-__device__ __forceinline__ void adj_patch_split(const YSrc& ysrc, int NB, const Tab& FT, Sink& sink) {
+__device__ __forceinline__ void adj_patch_split(const YSrc& ysrc, int NB, const Tab& FT, Sink& sink, int kt_first = 0,
+                                                int kt_step = 1) {
   static_assert(MT <= 4, "the split coefficients of larger windows do not fit in registers");
   const int lane = lane_id();
   const int r16 = lane & 15, g = lane >> 4;
@@ -570,7 +571,9 @@ __device__ __forceinline__ void adj_patch_split(const YSrc& ysrc, int NB, const 
       inv = 1.f / sc;
     }
   }
-  for (int kt2 = 0; kt2 < NB; ++kt2) {
+  // column tiles kt_first, kt_first + kt_step, ... (several waves may share
+  // a window)
+  for (int kt2 = kt_first; kt2 < NB; kt2 += kt_step) {
     // stage 1: S[c1][k2] = sum_c2 Y[c1][c2] conj(F[c2][k2]) for this tile
     f32x4 Sre[MT], Sim[MT];
 #pragma unroll

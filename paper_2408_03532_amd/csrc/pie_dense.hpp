@@ -310,7 +310,15 @@ __global__ __launch_bounds__(256) void k_pie_adjoint(PieArgs a, int c0) {
   } else {
     const int c = valid ? a.pos[j].y : a.bb_c0;
     DeltaSink sink{a.dpsi + dpsi_base(a, q, c), a.n, a.dstride, a.inv_n2};
-    if constexpr (K2 > 1) {
+    if constexpr (MT <= 4 && K2 == 1) {
+      // whole residual per wave (split, or the three-product first stage in
+      // FP32), the position's column tiles shared by its waves
+      const int first = blockIdx.y * nw + w, step = gridDim.y * nw;
+      if constexpr (Orient<PR>::TR)
+        adj_patch_split<PR, MT>(src, a.nb, T, sink, first, step);
+      else
+        adj_patch_f32<MT, 2>(src, a.nb, T, sink, first, step);
+    } else if constexpr (K2 > 1) {
       for (int gi = blockIdx.y * nw + w; gi * K2 < a.nb; gi += gridDim.y * nw)
         adj_tiles_f32<MT, K2>(src, a.nb, T, gi * K2, sink);
     } else {
