@@ -874,28 +874,31 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
 
 template <class PR, int MT>
 bool sequential_lds_prec(const PieArgs& a, size_t fa_bytes, size_t ft_bytes, hipStream_t st) {
-  // side-by-side teams only without probe step (which couples every
-  // position), for one tile of kept coefficients per axis (two tiles need
-  // more registers than two waves per SIMD leave), and where their LDS fits
-  int teams = (MT == 1 && !a.probe_step && a.J <= kSeqLevelMaxJ) ? 2 : 1;
-  SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes, teams);
-  if (teams == 2 && L.total > kSeqLdsBytes) {
-    teams = 1;
-    L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes, 1);
-  }
   // (the statistics read the whole object from one workgroup)
-  if (L.total > kSeqLdsBytes || (size_t)a.H * a.W > kSeqLdsMaxObject) return false;
+  if ((size_t)a.H * a.W > kSeqLdsMaxObject) return false;
+  // launches `kernel` when its static LDS and the layout for `nteams` fit
+  // the compute unit's LDS
   auto launch = [&](auto kernel, int nteams) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+    const SeqLdsLayout L = seq_lds_layout(a.bb_h, a.bb_w, a.n, a.m, a.J, fa_bytes, ft_bytes, nteams);
+    hipFuncAttributes attr{};
+    if (L.total > kSeqLdsBytes ||
+        hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(kernel)) != hipSuccess ||
+        L.total + attr.sharedSizeBytes > kMaxLdsTable ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)L.total) != hipSuccess)
       return false;
     hipLaunchKernelGGL(kernel, dim3(1), dim3(64 * kSeqWaves * nteams), L.total, st, a, fa_bytes, ft_bytes);
     return true;
   };
-  if constexpr (MT == 1)
-    if (teams == 2)
-      return a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true, 2>, 2)
-                           : launch(k_pie_sequential_lds<PR, MT, false, 2>, 2);
+  // side-by-side teams only without probe step (which couples every
+  // position) and for one tile of kept coefficients per axis (two tiles need
+  // more registers than two waves per SIMD leave); else one team
+  if constexpr (MT == 1) {
+    if (!a.probe_step && a.J <= kSeqLevelMaxJ &&
+        (a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true, 2>, 2)
+                       : launch(k_pie_sequential_lds<PR, MT, false, 2>, 2)))
+      return true;
+  }
   return a.n % 16 == 0 ? launch(k_pie_sequential_lds<PR, MT, true, 1>, 1)
                        : launch(k_pie_sequential_lds<PR, MT, false, 1>, 1);
 }

@@ -354,3 +354,23 @@ def test_sequential_sweep_of_mixed_overlap(pk, tiny, norm):
     assert rel(O, Or) <= 1e-5
     assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
     assert abs(st[0][1] - sr[1]) <= 1e-4 * sr[1]
+
+
+@pytest.mark.parametrize("box", [(96, 88), (96, 120), (100, 104), (112, 124)])
+def test_sequential_sweep_near_the_lds_limit(pk, tiny, box):
+    """batch = 1 with m = 32 over bounding boxes whose object rows, probe and
+    tables come close to the compute unit's LDS: whether the launch holds
+    them in LDS (its own static arrays counted) or falls back to the loop on
+    global memory, the sweep is eq. (5) in sweep order."""
+    h, w = box
+    n = tiny["probe"].shape[0]
+    m = 32
+    pos = np.asarray([(0, 0), (h - n, 0), (0, w - n), (h - n, w - n), ((h - n) // 2, (w - n) // 2)], dtype=np.int32)
+    inten = workloads.intensities(tiny["obj"], tiny["probe"], pos)
+    A, amp = amps(pk, inten, m)
+    case = dict(tiny, pos=pos)
+    params = dict(batch=1, norm=0, beta=1.0)
+    O, _, st = run_gpu(pk, case, tiny["init"], tiny["probe"], A, m, pk.PieParams(**params))
+    Or, _, sr = opie.pie_sweep(tiny["init"], tiny["probe"], pos, amp, m, **params)
+    assert rel(O, Or) <= 1e-5
+    assert abs(st[0][0] - sr[0]) <= 1e-5 * sr[0]
