@@ -589,7 +589,11 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
   // blocks (KS partial sums per row group)
   constexpr int KS = Orient<PR>::TR ? 1 : kSeqWaves / (WR * WC);
   constexpr int NP = WR * KS;  // partial spectra per column group
-  constexpr int PART = (NP > 1 ? (NP - 1) * WC : 1) * MT * CT * 2 * 64;
+  constexpr int PART = NP * WC * MT * CT * 2 * 64;  // every forward wave's partial spectrum
+  // projection elements per lane, e = ((wc * MT + c1t) * CT + ct) * 4 + i,
+  // shared out over the team's waves (element e to role e mod kSeqWaves)
+  constexpr int NE = WC * MT * CT * 4;
+  constexpr int EPW = (NE + kSeqWaves - 1) / kSeqWaves;
   static_assert(WR * WC <= kSeqWaves && KS >= 1, "the forward's waves must fit the team");
   extern __shared__ f32x4 dyn[];
   __shared__ f32x4 part[TEAMS][PART];
@@ -691,7 +695,6 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
   const TabL FT{(lds_cptr)(base + L.ft)};
   const int wc = wl % WC, wr = (wl / WC) % WR, kh = wl / (WC * WR);
   const bool fwd_role = wl < WR * WC * KS;
-  const bool proj_role = fwd_role && wr == 0 && kh == 0;  // sums the partials and projects
   const int pslot = kh * WR + wr;                         // partial index (0: the projecting wave)
   auto forward = [&](const auto& src, f32x4(&Yre)[MT][CT], f32x4(&Yim)[MT][CT]) {
     if constexpr (Orient<PR>::TR)
@@ -704,19 +707,25 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
   // this team's step of each round (-1: idle), and the projection's
   // amplitudes, requested one round ahead
   auto step_of = [&](int rd) { return TEAMS > 1 ? rtab[rd * TEAMS + team] : rd; };
-  float avn[MT][CT][4];
+  // element e of this lane: its (row, column) of the window's spectrum and
+  // the partial-spectrum slot and component holding it
+  auto element = [&](int e, int& slot, int& comp) {
+    const int i = e & 3, blk = e >> 2;  // blk = (wc * MT + c1t) * CT + ct
+    const int ct = blk % CT, c1t = (blk / CT) % MT, wce = blk / (CT * MT);
+    slot = (wce * MT + c1t) * CT + ct;
+    comp = i;
+    return tile_rc<Orient<PR>::TR>(c1t, wce * CT + ct, i, lane);
+  };
+  float avn[EPW];
   auto load_amp = [&](int t) {
-    const bool on = t >= 0 && proj_role;
-    const int j = on ? jl[t] : 0;
+    const int j = t >= 0 ? jl[t] : 0;
 #pragma unroll
-    for (int c1t = 0; c1t < MT; ++c1t)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
-          avn[c1t][ct][i] = (on && rc.x < m && rc.y < m) ? a.amp[(size_t)j * m * m + (size_t)rc.x * m + rc.y] : 0.f;
-        }
+    for (int k = 0; k < EPW; ++k) {
+      const int e = wl + k * kSeqWaves;
+      int slot, comp;
+      const int2 rc = element(e < NE ? e : 0, slot, comp);
+      avn[k] = (t >= 0 && e < NE && rc.x < m && rc.y < m) ? a.amp[(size_t)j * m * m + (size_t)rc.x * m + rc.y] : 0.f;
+    }
   };
   // (the rounds exchange data through LDS only, so their barriers leave the
   // amplitude prefetch in flight)
@@ -726,13 +735,9 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
     {
       const int t = step_of(round);
       const bool active = t >= 0;  // uniform over the team
-      float av[MT][CT][4];
+      float av[EPW];
 #pragma unroll
-      for (int c1t = 0; c1t < MT; ++c1t)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) av[c1t][ct][i] = avn[c1t][ct][i];
+      for (int k = 0; k < EPW; ++k) av[k] = avn[k];
       if (round + 1 < nrounds) load_amp(step_of(round + 1));
       const int2 rc0 = posl[active ? t : 0];
       const bool valid = active && rc0.x >= 0;
@@ -766,8 +771,8 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
             GatherSrc<EXACT> src{Ol, Pl, ldo, b.n, r, c, ldp};
             forward(src, Yre, Yim);
           }
-          if (NP > 1 && pslot > 0) {
-            f32x4* dst = part[team] + ((size_t)((pslot - 1) * WC + wc) * MT * CT * 2) * 64;
+          {
+            f32x4* dst = part[team] + ((size_t)(pslot * WC + wc) * MT * CT * 2) * 64;
 #pragma unroll
             for (int a1 = 0; a1 < MT; ++a1)
 #pragma unroll
@@ -778,29 +783,26 @@ __global__ __launch_bounds__(64 * kSeqWaves * TEAMS) void k_pie_sequential_lds(P
           }
         }
         lds_barrier();
-        if (active && proj_role) {
-#pragma unroll
-          for (int rr = 1; rr < NP; ++rr) {
-            const f32x4* src = part[team] + ((size_t)((rr - 1) * WC + wc) * MT * CT * 2) * 64;
-#pragma unroll
-            for (int a1 = 0; a1 < MT; ++a1)
-#pragma unroll
-              for (int b1 = 0; b1 < CT; ++b1) {
-                Yre[a1][b1] += src[((a1 * CT + b1) * 2 + 0) * 64 + lane];
-                Yim[a1][b1] += src[((a1 * CT + b1) * 2 + 1) * 64 + lane];
-              }
-          }
+        if (active) {
+          // this wave's share of the projection: each element summed over
+          // the partial spectra in slot order
+          const float* pf = reinterpret_cast<const float*>(part[team]);
           double phi = 0.0;
 #pragma unroll
-          for (int c1t = 0; c1t < MT; ++c1t)
+          for (int k = 0; k < EPW; ++k) {
+            const int e = wl + k * kSeqWaves;
+            if (e >= NE) break;
+            int slot, comp;
+            const int2 rc = element(e, slot, comp);
+            float ur = 0.f, ui = 0.f;
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int2 rc = tile_rc<Orient<PR>::TR>(c1t, wc * CT + ct, i, lane);
-                if (rc.x < m && rc.y < m)
-                  phi += pie_project_amp(b, 0, valid, rc.x, rc.y, Yre[c1t][ct][i], Yim[c1t][ct][i], av[c1t][ct][i]);
-              }
+            for (int p = 0; p < NP; ++p) {
+              const float* q = pf + (size_t)p * WC * MT * CT * 2 * 64 * 4;
+              ur += q[((slot * 2 + 0) * 64 + lane) * 4 + comp];
+              ui += q[((slot * 2 + 1) * 64 + lane) * 4 + comp];
+            }
+            if (rc.x < m && rc.y < m) phi += pie_project_amp(b, 0, valid, rc.x, rc.y, ur, ui, av[k]);
+          }
           if (!b.probe_pass) phi_acc += phi;
         }
         lds_barrier();
