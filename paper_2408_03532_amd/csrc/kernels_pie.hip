@@ -455,7 +455,9 @@ hipError_t launch_pie_sweep(const PieArgs& a, int batch, hipStream_t st) {
       done = pie_sequential_lds_f32(a, st);
     if (done) return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_pie_begin, dim3(ew_blocks(obj)), dim3(256), 0, st, a);
+  // (the object copy only where the statistics need it; else the per-position
+  // slots alone)
+  hipLaunchKernelGGL(k_pie_begin, dim3(ew_blocks(a.fuse_stats ? (size_t)a.J * 4 : obj)), dim3(256), 0, st, a);
   if (a.order) hipLaunchKernelGGL(k_pie_rank, dim3(ew_blocks((size_t)a.J)), dim3(256), 0, st, a);
   const int ntiles = a.tiles_x * a.tiles_y;
   const int pblocks = pie_probe_blocks(a.n);
