@@ -154,3 +154,23 @@ def test_zero_exit_wave_has_zero_subgradient(pk, precision, tol):
     assert rel(gO.cpu().numpy(), gOr) <= tol
     assert rel(gP.cpu().numpy(), gPr) <= tol
     assert np.all(np.isfinite(gO.cpu().numpy())) and np.all(np.isfinite(gP.cpu().numpy()))
+
+
+@pytest.mark.parametrize("n,m", [(40, 12), (64, 20)])
+def test_ragged_sizes_loss_and_gradient(pk, n, m):
+    """Windows that are not whole 16-pixel tiles (n = 40) or kept blocks that
+    are not (m = 12, 20): the kernels that hold the twiddle table in LDS and
+    whole windows per wave step aside for the general ones; same results."""
+    print("loss ragged", n, m, flush=True)
+    case = workloads.amp_loss_case(seed=6, size=200, n=n, m=m, grid=4, step=40, offset=8, radius=n / 3.0,
+                                   sigma_f=8.0)
+    O, P, A = to_dev(case)
+    scan = pk.Scan(case["pos"], O.shape, n, m)
+    Og = O.clone().requires_grad_(True)
+    Pg = P.clone().requires_grad_(True)
+    L = pk.amplitude_loss(Og, Pg, scan, A)
+    L.backward()
+    Lr, gOr, gPr = oloss.amp_loss_grad(case["obj"], case["probe"], case["pos"], case["amp"], m)
+    assert abs(L.item() - Lr) <= 1e-5 * Lr
+    assert rel(Og.grad.cpu().numpy(), gOr) <= 1e-4
+    assert rel(Pg.grad.cpu().numpy(), gPr) <= 1e-4
